@@ -1,0 +1,506 @@
+/*
+ * disc_oracle.c -- plain FP64 CPU oracle of DISC (test infrastructure).
+ *
+ * TEST INFRASTRUCTURE ONLY: the checker the HIP library is compared against.
+ * Only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load it; the product path never does. No code, header or table
+ * here is shared with the HIP library.
+ *
+ * Every step is written the slow, direct way, in FP64, in the order of
+ * Algorithm A1 of Zhen et al. (arXiv 1204.6295):
+ *   global shift (Sec. 2.3) -> pyramid (Sec. 2.3) -> per level:
+ *     warp (Sec. 2.1 model) -> patch moments (Eq. 3) -> a, b (Eq. 5, 6)
+ *     -> I'_s = a I_s + b (Sec. 2.2) -> force (Eq. 1, static-gradient term)
+ *     -> r := r + dr (A1 step 5) -> Gaussian on r (A1 step 6)
+ *   -> up-sample r to the next level (A1).
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *  - field convention m(x) = CT(x + r(x)) (Sec. 2.1), so the A1 update
+ *    "add dr" is r := r - u with u the Eq. 1 static-gradient force;
+ *  - all stencils (warp corners, patches, gradient, Gaussian, pyramid)
+ *    clamp indices to the volume (edge replicate);
+ *  - central-difference gradient in intensity per voxel;
+ *  - Gaussian taps exp(-k^2 / 2 sigma^2), |k| <= ceil(3 sigma), normalised;
+ *  - Eq. 5 divides by STD(S); where var(S) <= tau the static patch is flat,
+ *    its spread carries no information and only the first moment of Eq. 4
+ *    is matched: a := 1, b := E(M) - E(S). This keeps identical images an
+ *    exact fixed point;
+ *  - u := 0 where |m - f| < eps_d or the denominator is 0;
+ *  - the corrected image is always a * (original shifted CBCT) + b (Sec. 2.2);
+ *  - pyramid: 2x2x2 block mean; field up-sampling: 2 * trilinear at
+ *    (x + 1/2)/2 - 1/2.
+ */
+#include "disc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int clampi(int v, int n)
+{
+    if (v < 0) return 0;
+    if (v > n - 1) return n - 1;
+    return v;
+}
+
+static long lin(int x, int y, int z, int nx, int ny)
+{
+    return ((long)z * ny + y) * nx + x;
+}
+
+double orc_mean(const double* v, long n)
+{
+    double s = 0.0;
+    for (long i = 0; i < n; ++i) s += v[i];
+    return s / (double)n;
+}
+
+double orc_global_shift(const double* ct, const double* cbct0, long n, double* s)
+{
+    double dhu = orc_mean(ct, n) - orc_mean(cbct0, n);
+    for (long i = 0; i < n; ++i) s[i] = cbct0[i] + dhu;
+    return dhu;
+}
+
+void orc_downsample2(const double* in, int nx, int ny, int nz, double* out)
+{
+    int cx = (nx + 1) / 2, cy = (ny + 1) / 2, cz = (nz + 1) / 2;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < cz; ++z)
+        for (int y = 0; y < cy; ++y)
+            for (int x = 0; x < cx; ++x) {
+                double s = 0.0;
+                for (int dz = 0; dz < 2; ++dz)
+                    for (int dy = 0; dy < 2; ++dy)
+                        for (int dx = 0; dx < 2; ++dx)
+                            s += in[lin(clampi(2 * x + dx, nx), clampi(2 * y + dy, ny),
+                                        clampi(2 * z + dz, nz), nx, ny)];
+                out[lin(x, y, z, cx, cy)] = s / 8.0;
+            }
+}
+
+/* Trilinear interpolation at the continuous position (px, py, pz): the eight
+ * surrounding voxels weighted by the products of the 1-D linear weights;
+ * corner indices are clamped (edge replicate). */
+static double trilinear(const double* v, int nx, int ny, int nz,
+                        double px, double py, double pz)
+{
+    double fx = floor(px), fy = floor(py), fz = floor(pz);
+    double tx = px - fx, ty = py - fy, tz = pz - fz;
+    int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    double s = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? tx : 1.0 - tx) * (dy ? ty : 1.0 - ty) * (dz ? tz : 1.0 - tz);
+                s += w * v[lin(clampi(ix + dx, nx), clampi(iy + dy, ny), clampi(iz + dz, nz), nx, ny)];
+            }
+    return s;
+}
+
+/* Same as trilinear() but reading an FP32 volume. */
+static double trilinear_f(const float* v, int nx, int ny, int nz,
+                          double px, double py, double pz)
+{
+    double fx = floor(px), fy = floor(py), fz = floor(pz);
+    double tx = px - fx, ty = py - fy, tz = pz - fz;
+    int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    double s = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? tx : 1.0 - tx) * (dy ? ty : 1.0 - ty) * (dz ? tz : 1.0 - tz);
+                s += w * (double)v[lin(clampi(ix + dx, nx), clampi(iy + dy, ny), clampi(iz + dz, nz), nx, ny)];
+            }
+    return s;
+}
+
+void orc_upsample_field(const double* rc, int cnx, int cny, int cnz,
+                        double* rf, int fnx, int fny, int fnz)
+{
+    long nc = (long)cnx * cny * cnz, nf = (long)fnx * fny * fnz;
+    for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < fnz; ++z)
+            for (int y = 0; y < fny; ++y)
+                for (int x = 0; x < fnx; ++x) {
+                    double px = (x + 0.5) / 2.0 - 0.5;
+                    double py = (y + 0.5) / 2.0 - 0.5;
+                    double pz = (z + 0.5) / 2.0 - 0.5;
+                    rf[c * nf + lin(x, y, z, fnx, fny)] =
+                        2.0 * trilinear(rc + c * nc, cnx, cny, cnz, px, py, pz);
+                }
+    }
+}
+
+void orc_warp(const double* ct, const double* r, int nx, int ny, int nz, double* m)
+{
+    long n = (long)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = lin(x, y, z, nx, ny);
+                m[i] = trilinear(ct, nx, ny, nz, x + r[i], y + r[n + i], z + r[2 * n + i]);
+            }
+}
+
+/* Mean and centred variance of the clamped patch centred at (x, y, z). */
+static void patch_at(const double* img, int nx, int ny, int nz,
+                     int px, int py, int pz, int x, int y, int z,
+                     double* mu, double* var)
+{
+    int rx = px / 2, ry = py / 2, rz = pz / 2;
+    double n = (double)px * py * pz;
+    double s = 0.0;
+    for (int k = -rz; k <= rz; ++k)
+        for (int j = -ry; j <= ry; ++j)
+            for (int i = -rx; i <= rx; ++i)
+                s += img[lin(clampi(x + i, nx), clampi(y + j, ny), clampi(z + k, nz), nx, ny)];
+    double e = s / n;
+    double q = 0.0;
+    for (int k = -rz; k <= rz; ++k)
+        for (int j = -ry; j <= ry; ++j)
+            for (int i = -rx; i <= rx; ++i) {
+                double d = img[lin(clampi(x + i, nx), clampi(y + j, ny), clampi(z + k, nz), nx, ny)] - e;
+                q += d * d;
+            }
+    *mu = e;
+    *var = q / n;
+}
+
+static void patch_at_f(const float* img, int nx, int ny, int nz,
+                       int px, int py, int pz, int x, int y, int z,
+                       double* mu, double* var)
+{
+    int rx = px / 2, ry = py / 2, rz = pz / 2;
+    double n = (double)px * py * pz;
+    double s = 0.0;
+    for (int k = -rz; k <= rz; ++k)
+        for (int j = -ry; j <= ry; ++j)
+            for (int i = -rx; i <= rx; ++i)
+                s += (double)img[lin(clampi(x + i, nx), clampi(y + j, ny), clampi(z + k, nz), nx, ny)];
+    double e = s / n;
+    double q = 0.0;
+    for (int k = -rz; k <= rz; ++k)
+        for (int j = -ry; j <= ry; ++j)
+            for (int i = -rx; i <= rx; ++i) {
+                double d = (double)img[lin(clampi(x + i, nx), clampi(y + j, ny), clampi(z + k, nz), nx, ny)] - e;
+                q += d * d;
+            }
+    *mu = e;
+    *var = q / n;
+}
+
+void orc_patch_moments(const double* img, int nx, int ny, int nz,
+                       int px, int py, int pz, double* mu, double* var)
+{
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = lin(x, y, z, nx, ny);
+                patch_at(img, nx, ny, nz, px, py, pz, x, y, z, &mu[i], &var[i]);
+            }
+}
+
+/* Eq. 5 and Eq. 6 for one voxel; a flat static patch (var_s <= tau) matches
+ * the mean only (a = 1). */
+static void match_moments(double mu_m, double var_m, double mu_s, double var_s,
+                          double tau, double* a, double* b)
+{
+    double av = (var_s > tau) ? sqrt(var_m / var_s) : 1.0;
+    *a = av;
+    *b = mu_m - av * mu_s;
+}
+
+void orc_correct(const double* mu_m, const double* var_m,
+                 const double* mu_s, const double* var_s,
+                 const double* s, long n, double tau,
+                 double* a, double* b, double* f)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        double av, bv;
+        match_moments(mu_m[i], var_m[i], mu_s[i], var_s[i], tau, &av, &bv);
+        if (a) a[i] = av;
+        if (b) b[i] = bv;
+        f[i] = av * s[i] + bv;
+    }
+}
+
+/* Eq. 1 static-gradient term at one voxel: d = m - f, g = central-difference
+ * gradient of f. Writes the three components of u. */
+static void force_from(double d, double gx, double gy, double gz, double eps_d, double u[3])
+{
+    double den = gx * gx + gy * gy + gz * gz + d * d;
+    if (den > 0.0 && fabs(d) >= eps_d) {
+        u[0] = d * gx / den;
+        u[1] = d * gy / den;
+        u[2] = d * gz / den;
+    } else {
+        u[0] = u[1] = u[2] = 0.0;
+    }
+}
+
+void orc_force(const double* m, const double* f, int nx, int ny, int nz,
+               double eps_d, double* u)
+{
+    long n = (long)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = lin(x, y, z, nx, ny);
+                double gx = (f[lin(clampi(x + 1, nx), y, z, nx, ny)] - f[lin(clampi(x - 1, nx), y, z, nx, ny)]) / 2.0;
+                double gy = (f[lin(x, clampi(y + 1, ny), z, nx, ny)] - f[lin(x, clampi(y - 1, ny), z, nx, ny)]) / 2.0;
+                double gz = (f[lin(x, y, clampi(z + 1, nz), nx, ny)] - f[lin(x, y, clampi(z - 1, nz), nx, ny)]) / 2.0;
+                double uu[3];
+                force_from(m[i] - f[i], gx, gy, gz, eps_d, uu);
+                u[i] = uu[0];
+                u[n + i] = uu[1];
+                u[2 * n + i] = uu[2];
+            }
+}
+
+int orc_gauss_taps(double sigma, double* w)
+{
+    if (!(sigma > 0.0)) return -1;
+    int R = (int)ceil(3.0 * sigma);
+    if (R > 64) return -1;
+    double s = 0.0;
+    for (int k = -R; k <= R; ++k) {
+        w[k + R] = exp(-(double)k * k / (2.0 * sigma * sigma));
+        s += w[k + R];
+    }
+    for (int k = 0; k <= 2 * R; ++k) w[k] /= s;
+    return R;
+}
+
+void orc_gauss(const double* in, int nx, int ny, int nz, double sigma, double* out)
+{
+    double w[129];
+    int R = orc_gauss_taps(sigma, w);
+    long n = (long)nx * ny * nz;
+    double* t1 = (double*)malloc(sizeof(double) * n);
+    double* t2 = (double*)malloc(sizeof(double) * n);
+    /* x pass */
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double s = 0.0;
+                for (int k = -R; k <= R; ++k) s += w[k + R] * in[lin(clampi(x + k, nx), y, z, nx, ny)];
+                t1[lin(x, y, z, nx, ny)] = s;
+            }
+    /* y pass */
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double s = 0.0;
+                for (int k = -R; k <= R; ++k) s += w[k + R] * t1[lin(x, clampi(y + k, ny), z, nx, ny)];
+                t2[lin(x, y, z, nx, ny)] = s;
+            }
+    /* z pass */
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                double s = 0.0;
+                for (int k = -R; k <= R; ++k) s += w[k + R] * t2[lin(x, y, clampi(z + k, nz), nx, ny)];
+                out[lin(x, y, z, nx, ny)] = s;
+            }
+    free(t1);
+    free(t2);
+}
+
+void orc_iterate(const double* ct, const double* s, const double* mu_s,
+                 const double* var_s, double* r, int nx, int ny, int nz,
+                 const orc_params* p, double* m_out, double* f_out, double* rt_out)
+{
+    long n = (long)nx * ny * nz;
+    double* m = (double*)malloc(sizeof(double) * n);
+    double* mu_m = (double*)malloc(sizeof(double) * n);
+    double* var_m = (double*)malloc(sizeof(double) * n);
+    double* f = (double*)malloc(sizeof(double) * n);
+    double* u = (double*)malloc(sizeof(double) * 3 * n);
+
+    /* deformed moving image I_m^(k) */
+    orc_warp(ct, r, nx, ny, nz, m);
+    /* A1 step 1: patch moments (Eq. 3) and a, b (Eq. 5, 6); step 3: I'_s */
+    orc_patch_moments(m, nx, ny, nz, p->patch[0], p->patch[1], p->patch[2], mu_m, var_m);
+    orc_correct(mu_m, var_m, mu_s, var_s, s, n, p->var_floor, NULL, NULL, f);
+    /* A1 step 4: Eq. 1 force on I'_s; step 5: add dr = -u to r */
+    orc_force(m, f, nx, ny, nz, p->diff_floor, u);
+    for (long i = 0; i < 3 * n; ++i) r[i] -= u[i];
+    if (rt_out) memcpy(rt_out, r, sizeof(double) * 3 * n);
+    /* A1 step 6: Gaussian on each component of r */
+    for (int c = 0; c < 3; ++c) {
+        orc_gauss(r + c * n, nx, ny, nz, p->sigma, u + c * n);
+        memcpy(r + c * n, u + c * n, sizeof(double) * n);
+    }
+    if (m_out) memcpy(m_out, m, sizeof(double) * n);
+    if (f_out) memcpy(f_out, f, sizeof(double) * n);
+    free(m);
+    free(mu_m);
+    free(var_m);
+    free(f);
+    free(u);
+}
+
+int orc_register(const double* ct, const double* cbct0, int nx, int ny, int nz,
+                 const orc_params* p, double* r_out, double* f_out)
+{
+    if (!ct || !cbct0 || !p || !r_out || nx < 1 || ny < 1 || nz < 1) return -1;
+    if (p->levels < 1 || p->levels > 8 || !(p->sigma > 0.0)) return -1;
+    for (int d = 0; d < 3; ++d)
+        if (p->patch[d] < 1 || p->patch[d] % 2 == 0) return -1;
+
+    int L = p->levels;
+    int dims[8][3];
+    double* cts[8];
+    double* ss[8];
+    long ns[8];
+    dims[L - 1][0] = nx;
+    dims[L - 1][1] = ny;
+    dims[L - 1][2] = nz;
+    for (int l = L - 2; l >= 0; --l)
+        for (int d = 0; d < 3; ++d) dims[l][d] = (dims[l + 1][d] + 1) / 2;
+    for (int l = 0; l < L; ++l) ns[l] = (long)dims[l][0] * dims[l][1] * dims[l][2];
+
+    /* A1: globally adjust the CBCT intensity (Sec. 2.3) */
+    long n = ns[L - 1];
+    cts[L - 1] = (double*)malloc(sizeof(double) * n);
+    ss[L - 1] = (double*)malloc(sizeof(double) * n);
+    memcpy(cts[L - 1], ct, sizeof(double) * n);
+    if (p->global_shift)
+        orc_global_shift(ct, cbct0, n, ss[L - 1]);
+    else
+        memcpy(ss[L - 1], cbct0, sizeof(double) * n);
+
+    /* A1: down-sample to the coarsest resolution */
+    for (int l = L - 2; l >= 0; --l) {
+        cts[l] = (double*)malloc(sizeof(double) * ns[l]);
+        ss[l] = (double*)malloc(sizeof(double) * ns[l]);
+        orc_downsample2(cts[l + 1], dims[l + 1][0], dims[l + 1][1], dims[l + 1][2], cts[l]);
+        orc_downsample2(ss[l + 1], dims[l + 1][0], dims[l + 1][1], dims[l + 1][2], ss[l]);
+    }
+
+    /* A1: initialise r to zero */
+    double* r = (double*)calloc(3 * ns[0], sizeof(double));
+    double* f = NULL;
+
+    for (int l = 0; l < L; ++l) {
+        int lx = dims[l][0], ly = dims[l][1], lz = dims[l][2];
+        if (l > 0) {
+            double* rf = (double*)malloc(sizeof(double) * 3 * ns[l]);
+            orc_upsample_field(r, dims[l - 1][0], dims[l - 1][1], dims[l - 1][2], rf, lx, ly, lz);
+            free(r);
+            r = rf;
+        }
+        /* the static image is the original (shifted) CBCT at every iteration
+         * (Sec. 2.2), so its patch moments are fixed for the level */
+        double* mu_s = (double*)malloc(sizeof(double) * ns[l]);
+        double* var_s = (double*)malloc(sizeof(double) * ns[l]);
+        orc_patch_moments(ss[l], lx, ly, lz, p->patch[0], p->patch[1], p->patch[2], mu_s, var_s);
+        free(f);
+        f = (double*)malloc(sizeof(double) * ns[l]);
+        for (long i = 0; i < ns[l]; ++i) f[i] = ss[l][i];
+        for (int k = 0; k < p->iters[l]; ++k)
+            orc_iterate(cts[l], ss[l], mu_s, var_s, r, lx, ly, lz, p, NULL, f, NULL);
+        free(mu_s);
+        free(var_s);
+    }
+    memcpy(r_out, r, sizeof(double) * 3 * n);
+    if (f_out) memcpy(f_out, f, sizeof(double) * n);
+    free(r);
+    free(f);
+    for (int l = 0; l < L; ++l) {
+        free(cts[l]);
+        free(ss[l]);
+    }
+    return 0;
+}
+
+/* ---- point evaluators ---------------------------------------------------- */
+
+static void unlin(long i, int nx, int ny, int* x, int* y, int* z)
+{
+    *x = (int)(i % nx);
+    *y = (int)((i / nx) % ny);
+    *z = (int)(i / ((long)nx * ny));
+}
+
+void orc_warp_pts(const float* ct, const float* r, int nx, int ny, int nz,
+                  const long* pts, long npts, double* out)
+{
+    long n = (long)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < npts; ++q) {
+        int x, y, z;
+        long i = pts[q];
+        unlin(i, nx, ny, &x, &y, &z);
+        out[q] = trilinear_f(ct, nx, ny, nz, x + (double)r[i], y + (double)r[n + i],
+                             z + (double)r[2 * n + i]);
+    }
+}
+
+void orc_correct_pts(const float* m, const float* s, int nx, int ny, int nz,
+                     int px, int py, int pz, double tau,
+                     const long* pts, long npts, double* out)
+{
+#pragma omp parallel for schedule(dynamic)
+    for (long q = 0; q < npts; ++q) {
+        int x, y, z;
+        long i = pts[q];
+        unlin(i, nx, ny, &x, &y, &z);
+        double mu_m, var_m, mu_s, var_s, a, b;
+        patch_at_f(m, nx, ny, nz, px, py, pz, x, y, z, &mu_m, &var_m);
+        patch_at_f(s, nx, ny, nz, px, py, pz, x, y, z, &mu_s, &var_s);
+        match_moments(mu_m, var_m, mu_s, var_s, tau, &a, &b);
+        out[q] = a * (double)s[i] + b;
+    }
+}
+
+void orc_force_pts(const float* m, const float* f, const float* r,
+                   int nx, int ny, int nz, double eps_d,
+                   const long* pts, long npts, double* out)
+{
+    long n = (long)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < npts; ++q) {
+        int x, y, z;
+        long i = pts[q];
+        unlin(i, nx, ny, &x, &y, &z);
+        double gx = ((double)f[lin(clampi(x + 1, nx), y, z, nx, ny)] - (double)f[lin(clampi(x - 1, nx), y, z, nx, ny)]) / 2.0;
+        double gy = ((double)f[lin(x, clampi(y + 1, ny), z, nx, ny)] - (double)f[lin(x, clampi(y - 1, ny), z, nx, ny)]) / 2.0;
+        double gz = ((double)f[lin(x, y, clampi(z + 1, nz), nx, ny)] - (double)f[lin(x, y, clampi(z - 1, nz), nx, ny)]) / 2.0;
+        double u[3];
+        force_from((double)m[i] - (double)f[i], gx, gy, gz, eps_d, u);
+        for (int c = 0; c < 3; ++c) out[3 * q + c] = (double)r[c * n + i] - u[c];
+    }
+}
+
+void orc_gauss_pts(const float* rt, int nx, int ny, int nz, double sigma,
+                   const long* pts, long npts, double* out)
+{
+    double w[129];
+    int R = orc_gauss_taps(sigma, w);
+    long n = (long)nx * ny * nz;
+#pragma omp parallel for schedule(dynamic)
+    for (long q = 0; q < npts; ++q) {
+        int x, y, z;
+        long i = pts[q];
+        unlin(i, nx, ny, &x, &y, &z);
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int k = -R; k <= R; ++k)
+                for (int j = -R; j <= R; ++j)
+                    for (int ii = -R; ii <= R; ++ii)
+                        s += w[k + R] * w[j + R] * w[ii + R] *
+                             (double)rt[c * n + lin(clampi(x + ii, nx), clampi(y + j, ny), clampi(z + k, nz), nx, ny)];
+            out[3 * q + c] = s;
+        }
+    }
+}

@@ -1,0 +1,123 @@
+/*
+ * disc_oracle.h -- plain FP64 CPU oracle of DISC (test infrastructure).
+ *
+ * TEST INFRASTRUCTURE ONLY: the checker the HIP library is compared against.
+ * Only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load it. It shares no code, header, table or helper with the HIP
+ * library, and the HIP library never calls it.
+ *
+ * Method: Zhen, Gu, Yan, Zhou, Jia, Jiang, "CT to Cone-beam CT Deformable
+ * Registration With Simultaneous Intensity Correction" (arXiv 1204.6295),
+ * Sec. 2.1 (Eq. 1), Sec. 2.2 (Eq. 2-6 and Appendix A.1-A.7), Sec. 2.3
+ * (global shift, multi-scale strategy) and Algorithm A1.
+ *
+ * Layout: scalar volumes are [nz][ny][nx] with x fastest; vector fields are
+ * [3][nz][ny][nx], components (x, y, z), in voxel units. Arrays passed as
+ * double are full FP64 volumes; the *_pts functions read FP32 state (the
+ * precision a GPU stores) and promote every value to FP64 on load.
+ *
+ * Parity status: every function here is pinned by the CPU test-suite
+ * (library routines, closed forms, invariants, brute force). The Eq. 7-10
+ * mask/fill and the stopping criterion are not part of this oracle.
+ */
+#ifndef DISC_ORACLE_H
+#define DISC_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int    patch[3];     /* odd patch extents (px, py, pz), Eq. 3 patch of n = px*py*pz voxels */
+    double sigma;        /* Gaussian regularisation sigma, voxels */
+    int    levels;       /* pyramid levels, 2x per level (Sec. 2.3) */
+    int    iters[8];     /* iterations per level, coarsest first */
+    int    global_shift; /* 1: shift CBCT by the mean difference (Sec. 2.3) */
+    double var_floor;    /* tau: a static-patch variance <= tau counts as flat (a := 1) */
+    double diff_floor;   /* eps_d: |m - f'| < eps_d gives a zero force */
+} orc_params;
+
+/* Sec. 2.3: plain mean over all voxels. */
+double orc_mean(const double* v, long n);
+
+/* Sec. 2.3 global intensity adjustment: Delta HU = mean(CT) - mean(CBCT);
+ * s = cbct0 + Delta HU. Returns Delta HU. (The hot path is invariant to this
+ * shift: b absorbs any constant added to the static image.) */
+double orc_global_shift(const double* ct, const double* cbct0, long n, double* s);
+
+/* Multi-scale strategy (Sec. 2.3): 2x2x2 block mean, indices clamped,
+ * output dims ceil(n/2). */
+void orc_downsample2(const double* in, int nx, int ny, int nz, double* out);
+
+/* Algorithm A1, last step: r_f(x) = 2 * trilinear(r_c, (x + 1/2)/2 - 1/2). */
+void orc_upsample_field(const double* rc, int cnx, int cny, int cnz,
+                        double* rf, int fnx, int fny, int fnz);
+
+/* Sec. 2.1 model I_m(x + v(x)) = I_s(x): m(x) = CT(x + r(x)), trilinear,
+ * edge replicated. */
+void orc_warp(const double* ct, const double* r, int nx, int ny, int nz, double* m);
+
+/* Eq. 3 (p = 1 and the centred second moment used in Eq. 5): patch mean and
+ * population variance over the clamped px*py*pz patch at every voxel. */
+void orc_patch_moments(const double* img, int nx, int ny, int nz,
+                       int px, int py, int pz, double* mu, double* var);
+
+/* Eq. 5, 6 and Sec. 2.2 I'_s = a I_s + b. Where var_s <= tau (flat static
+ * patch) only the mean is matched: a = 1. */
+void orc_correct(const double* mu_m, const double* var_m,
+                 const double* mu_s, const double* var_s,
+                 const double* s, long n, double tau,
+                 double* a, double* b, double* f);
+
+/* Eq. 1, static-gradient term, on the corrected static image f = I'_s:
+ * u = (m - f) grad f / (|grad f|^2 + (m - f)^2); central differences,
+ * indices clamped. u is a field [3][N]. */
+void orc_force(const double* m, const double* f, int nx, int ny, int nz,
+               double eps_d, double* u);
+
+/* Truncated, normalised Gaussian taps w[0..2R], R = ceil(3 sigma).
+ * Returns R (<= 64) or -1 when sigma is not positive. */
+int orc_gauss_taps(double sigma, double* w);
+
+/* Algorithm A1 step 6: separable Gaussian of one scalar volume (x, y, z
+ * passes), indices clamped. */
+void orc_gauss(const double* in, int nx, int ny, int nz, double sigma, double* out);
+
+/* One DISC iteration at one level (Algorithm A1 steps 1, 3-6):
+ * m = warp(ct, r); moments of m; f = a s + b; u = force; r = G * (r - u).
+ * mu_s / var_s are the patch moments of s. r is updated in place.
+ * m_out, f_out and rt_out (r - u before smoothing) may be NULL. */
+void orc_iterate(const double* ct, const double* s, const double* mu_s,
+                 const double* var_s, double* r, int nx, int ny, int nz,
+                 const orc_params* p, double* m_out, double* f_out, double* rt_out);
+
+/* Whole Algorithm A1 with fixed iteration counts. r_out: finest field [3][N];
+ * f_out: I'_s of the last iteration at the finest level (N). Returns 0, or -1
+ * on invalid arguments. */
+int orc_register(const double* ct, const double* cbct0, int nx, int ny, int nz,
+                 const orc_params* p, double* r_out, double* f_out);
+
+/* ---- point evaluators on FP32 state (sampled parity at full size) ------ */
+
+/* m at the listed voxels (linear indices) from FP32 ct and r. */
+void orc_warp_pts(const float* ct, const float* r, int nx, int ny, int nz,
+                  const long* pts, long npts, double* out);
+
+/* I'_s at the listed voxels from FP32 m and FP32 static image s. */
+void orc_correct_pts(const float* m, const float* s, int nx, int ny, int nz,
+                     int px, int py, int pz, double tau,
+                     const long* pts, long npts, double* out);
+
+/* r - u at the listed voxels from FP32 m, f, r; out is [npts][3]. */
+void orc_force_pts(const float* m, const float* f, const float* r,
+                   int nx, int ny, int nz, double eps_d,
+                   const long* pts, long npts, double* out);
+
+/* Gaussian of the FP32 field rt at the listed voxels; out is [npts][3]. */
+void orc_gauss_pts(const float* rt, int nx, int ny, int nz, double sigma,
+                   const long* pts, long npts, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

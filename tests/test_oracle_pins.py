@@ -1,0 +1,407 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks one oracle function against an independent reference: a
+library routine (scipy.ndimage), a closed form, an invariant that follows
+from the paper's equations, a hand-worked example, or brute force. A planted
+mistake in any oracle step (dropped term, wrong sign, transposed axis, wrong
+clamp) fails at least one of them.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+from synth.phantom import make_case, smooth_blob_pair
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng(seed):
+    return np.random.default_rng([7, seed])
+
+
+# --------------------------------------------------------------------------
+# Eq. 3 patch moments
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(11, 10, 9), (7, 6, 5), (2, 4, 3)])
+@pytest.mark.parametrize("patch", [(3, 3, 3), (5, 3, 1), (5, 5, 5), (1, 1, 1), (7, 9, 3), (13, 1, 5)])
+def test_patch_moments_vs_uniform_filter(shape, patch):
+    """Clamped box mean == scipy uniform_filter(mode='nearest'); the variance
+    equals E[x^2] - E[x]^2 from the same library filter."""
+    img = rng(1).normal(size=shape) * 300.0 + 40.0
+    mu, var = oracle.patch_moments(img, patch)
+    size = (patch[2], patch[1], patch[0])  # array axes are (z, y, x)
+    mu_ref = ndi.uniform_filter(img, size=size, mode="nearest")
+    m2_ref = ndi.uniform_filter(img * img, size=size, mode="nearest")
+    np.testing.assert_allclose(mu, mu_ref, rtol=0, atol=1e-10 * np.abs(img).max())
+    np.testing.assert_allclose(var, m2_ref - mu_ref ** 2, rtol=0, atol=1e-9 * (img ** 2).max())
+
+
+def test_patch_moments_brute_force():
+    """Per-voxel loops over an explicitly clamped patch, numpy mean/var."""
+    nz, ny, nx = 4, 5, 6
+    img = rng(2).uniform(-1000, 1500, size=(nz, ny, nx))
+    px, py, pz = 3, 5, 1
+    mu, var = oracle.patch_moments(img, (px, py, pz))
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                vals = []
+                for k in range(-(pz // 2), pz // 2 + 1):
+                    for j in range(-(py // 2), py // 2 + 1):
+                        for i in range(-(px // 2), px // 2 + 1):
+                            vals.append(img[min(max(z + k, 0), nz - 1), min(max(y + j, 0), ny - 1),
+                                            min(max(x + i, 0), nx - 1)])
+                assert len(vals) == px * py * pz
+                assert abs(mu[z, y, x] - np.mean(vals)) < 1e-10
+                assert abs(var[z, y, x] - np.var(vals)) < 1e-8
+
+
+def test_patch_moments_linear_closed_form():
+    """For m = ax + by + cz + e, away from the border the patch mean is the
+    centre value and the variance is sum a_d^2 (p_d^2 - 1)/12."""
+    nz, ny, nx = 20, 21, 22
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    a, b, c, e = 3.5, -2.0, 7.25, -400.0
+    img = a * x + b * y + c * z + e
+    patch = (5, 7, 3)
+    mu, var = oracle.patch_moments(img, patch)
+    R = [p // 2 for p in patch]
+    sl = (slice(R[2], nz - R[2]), slice(R[1], ny - R[1]), slice(R[0], nx - R[0]))
+    np.testing.assert_allclose(mu[sl], img[sl], atol=1e-9)
+    expect = a * a * (patch[0] ** 2 - 1) / 12 + b * b * (patch[1] ** 2 - 1) / 12 + c * c * (patch[2] ** 2 - 1) / 12
+    np.testing.assert_allclose(var[sl], expect, rtol=1e-11)
+    # at the x = 0 border of a 1-D ramp with a 3-patch the clamped values are {0, 0, 1}
+    mu1, var1 = oracle.patch_moments(np.arange(5.0).reshape(1, 1, 5), (3, 1, 1))
+    assert abs(mu1[0, 0, 0] - 1 / 3) < 1e-15 and abs(var1[0, 0, 0] - 2 / 9) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Eq. 5-6 and I'_s: hand-worked example and the Appendix identity
+# --------------------------------------------------------------------------
+
+def test_worked_example_golden():
+    g = json.load(open(os.path.join(GOLDEN, "moment_match_3voxel.json")))
+    m = np.array(g["m"]).reshape(1, 1, 3)
+    s = np.array(g["s"]).reshape(1, 1, 3)
+    mu_m, var_m = oracle.patch_moments(m, g["patch"])
+    mu_s, var_s = oracle.patch_moments(s, g["patch"])
+    for k in range(3):
+        assert Fraction(g["mu_m"][k]) == Fraction(mu_m.flat[k]).limit_denominator(1000)
+        assert Fraction(g["var_m"][k]) == Fraction(var_m.flat[k]).limit_denominator(1000)
+        assert Fraction(g["mu_s"][k]) == Fraction(mu_s.flat[k]).limit_denominator(1000)
+        assert Fraction(g["var_s"][k]) == Fraction(var_s.flat[k]).limit_denominator(1000)
+    a, b, f = oracle.correct(mu_m, var_m, mu_s, var_s, s)
+    np.testing.assert_allclose(a.ravel(), g["a_value"], rtol=1e-13)
+    np.testing.assert_allclose(b.ravel(), g["b_value"], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(f.ravel(), g["f_value"], rtol=1e-13)
+    u = oracle.force(m, f)
+    np.testing.assert_allclose(u[0].ravel(), g["u_x_value"], rtol=1e-12, atol=1e-15)
+    assert np.all(u[1] == 0) and np.all(u[2] == 0)
+
+
+def test_appendix_identity_moments_matched():
+    """Appendix A.2-A.3: the transformed patch a S_P + b has mean E(M) and
+    variance var(M) at every voxel whose static patch is not flat."""
+    shape = (6, 7, 8)
+    patch = (3, 5, 3)
+    m = rng(3).normal(size=shape) * 200.0 + 50.0
+    s = rng(4).normal(size=shape) * 30.0 - 100.0
+    mu_m, var_m = oracle.patch_moments(m, patch)
+    mu_s, var_s = oracle.patch_moments(s, patch)
+    a, b, f = oracle.correct(mu_m, var_m, mu_s, var_s, s)
+    nz, ny, nx = shape
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                zi = np.clip(np.arange(z - 1, z + 2), 0, nz - 1)
+                yi = np.clip(np.arange(y - 2, y + 3), 0, ny - 1)
+                xi = np.clip(np.arange(x - 1, x + 2), 0, nx - 1)
+                SP = s[np.ix_(zi, yi, xi)].ravel()
+                MP = m[np.ix_(zi, yi, xi)].ravel()
+                SPc = a[z, y, x] * SP + b[z, y, x]
+                assert abs(SPc.mean() - MP.mean()) < 1e-9
+                assert abs(SPc.var() - MP.var()) < 1e-7 * MP.var()
+                assert a[z, y, x] > 0
+
+
+def test_flat_static_patch_matches_mean_only():
+    shape = (5, 5, 5)
+    m = rng(5).normal(size=shape) * 10
+    s = np.full(shape, 123.0)
+    mu_m, var_m = oracle.patch_moments(m, (3, 3, 3))
+    mu_s, var_s = oracle.patch_moments(s, (3, 3, 3))
+    a, b, f = oracle.correct(mu_m, var_m, mu_s, var_s, s)
+    assert np.all(a == 1.0)
+    np.testing.assert_allclose(f, mu_m, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Eq. 1 force
+# --------------------------------------------------------------------------
+
+def test_force_bounded_by_half():
+    """AM-GM on Eq. 1's single term: |u| = |d| |g| / (|g|^2 + d^2) <= 1/2."""
+    shape = (9, 10, 11)
+    m = rng(6).normal(size=shape) * 500
+    f = rng(7).normal(size=shape) * 500
+    u = oracle.force(m, f)
+    mag = np.sqrt((u ** 2).sum(0))
+    assert mag.max() <= 0.5 + 1e-15
+    assert mag.max() > 0.3
+
+
+def test_force_direction_and_floor():
+    """On f = ramp along x and m = f + d: u = d g / (g^2 + d^2) along x only;
+    |d| below eps_d gives u = 0 exactly."""
+    nx = 12
+    f = np.tile(np.arange(nx, dtype=float) * 4.0, (3, 5, 1))
+    for d, expect in [(2.0, 2 * 4 / (16 + 4)), (-8.0, -8 * 4 / (16 + 64)), (5e-4, 0.0)]:
+        u = oracle.force(f + d, f, eps_d=1e-3)
+        np.testing.assert_allclose(u[0][:, :, 1:-1], expect, rtol=1e-14)
+        assert np.all(u[1] == 0) and np.all(u[2] == 0)
+    # clamped border: the central difference becomes (f1 - f0) / 2
+    u = oracle.force(f + 2.0, f)
+    assert abs(u[0][0, 0, 0] - 2 * 2 / (4 + 4)) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Gaussian regularisation
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sigma", [0.7, 1.1, 1.5, 2.0])
+def test_gauss_vs_scipy(sigma):
+    v = rng(8).normal(size=(9, 14, 17))
+    R = int(np.ceil(3 * sigma))
+    ref = ndi.gaussian_filter(v, sigma=sigma, mode="nearest", radius=R)
+    np.testing.assert_allclose(oracle.gauss(v, sigma), ref, atol=1e-13)
+    w = oracle.gauss_taps(sigma)
+    assert len(w) == 2 * R + 1 and abs(w.sum() - 1) < 1e-15
+
+
+def test_gauss_direct_3d_and_invariants():
+    sigma = 1.5
+    v = rng(9).normal(size=(7, 8, 9))
+    w = oracle.gauss_taps(sigma)
+    k3 = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    ref = ndi.correlate(v, k3, mode="nearest")
+    np.testing.assert_allclose(oracle.gauss(v, sigma), ref, atol=1e-13)
+    # constants are preserved
+    c = np.full((6, 7, 8), -3.25)
+    np.testing.assert_allclose(oracle.gauss(c, 2.0), c, atol=1e-14)
+    # linear fields are preserved away from the border
+    z, y, x = np.meshgrid(np.arange(20), np.arange(20), np.arange(20), indexing="ij")
+    lin = 0.3 * x - 0.2 * y + 0.1 * z
+    g = oracle.gauss(lin.astype(float), 1.5)
+    np.testing.assert_allclose(g[5:-5, 5:-5, 5:-5], lin[5:-5, 5:-5, 5:-5], atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# warp (Sec. 2.1 model), pyramid and up-sampling (Sec. 2.3, A1)
+# --------------------------------------------------------------------------
+
+def test_warp_vs_map_coordinates():
+    shape = (8, 9, 10)
+    ct = rng(10).normal(size=shape) * 400
+    r = rng(11).uniform(-3.5, 3.5, size=(3,) + shape)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    coords = np.stack([z + r[2], y + r[1], x + r[0]])
+    ref = ndi.map_coordinates(ct, coords, order=1, mode="nearest")
+    np.testing.assert_allclose(oracle.warp(ct, r), ref, atol=1e-10)
+
+
+def test_warp_special_cases():
+    shape = (6, 7, 8)
+    ct = rng(12).normal(size=shape) * 400
+    assert np.array_equal(oracle.warp(ct, np.zeros((3,) + shape)), ct)
+    # integer shift (2, -1, 1): interior equals the shifted image bitwise
+    r = np.stack([np.full(shape, 2.0), np.full(shape, -1.0), np.full(shape, 1.0)])
+    m = oracle.warp(ct, r)
+    assert np.array_equal(m[:-1, 1:, :-2], ct[1:, :-1, 2:])
+    # trilinear reproduces linear functions exactly inside the volume
+    z, y, x = np.meshgrid(np.arange(6), np.arange(7), np.arange(8), indexing="ij")
+    lin = 2 * x - 3 * y + 5 * z + 1.0
+    rr = rng(13).uniform(-0.4, 0.4, size=(3,) + shape)
+    ml = oracle.warp(lin, rr)
+    expect = 2 * (x + rr[0]) - 3 * (y + rr[1]) + 5 * (z + rr[2]) + 1
+    sl = (slice(1, -1),) * 3
+    np.testing.assert_allclose(ml[sl], expect[sl], atol=1e-12)
+
+
+def test_global_shift_matches_means():
+    """Sec. 2.3: the shifted CBCT has the CT's mean; Delta HU has the CT-minus-CBCT sign."""
+    ct = rng(20).normal(size=(5, 6, 7)) * 100 + 30.0
+    cb = rng(21).normal(size=(5, 6, 7)) * 100 - 170.0
+    dhu, s = oracle.global_shift(ct, cb)
+    assert abs(dhu - (ct.mean() - cb.mean())) < 1e-10 and dhu > 150
+    assert abs(s.mean() - ct.mean()) < 1e-10
+    np.testing.assert_allclose(s - cb, dhu, atol=1e-12)
+
+
+def test_downsample_and_upsample():
+    v = rng(14).normal(size=(6, 8, 10))
+    ref = v.reshape(3, 2, 4, 2, 5, 2).mean(axis=(1, 3, 5))
+    np.testing.assert_allclose(oracle.downsample2(v), ref, atol=1e-14)
+    # odd sizes: the last block repeats the edge plane
+    w = rng(15).normal(size=(5, 3, 7))
+    pad = np.pad(w, ((0, 1), (0, 1), (0, 1)), mode="edge")
+    ref = pad.reshape(3, 2, 2, 2, 4, 2).mean(axis=(1, 3, 5))
+    np.testing.assert_allclose(oracle.downsample2(w), ref, atol=1e-14)
+    assert np.all(oracle.downsample2(np.full((5, 5, 5), 7.5)) == 7.5)
+    # up-sampling: 2 * trilinear at (x + 1/2)/2 - 1/2
+    rc = rng(16).normal(size=(3, 4, 5, 6))
+    fine = (8, 10, 11)
+    up = oracle.upsample_field(rc, fine)
+    z, y, x = np.meshgrid(*[(np.arange(n) + 0.5) / 2 - 0.5 for n in fine], indexing="ij")
+    for c in range(3):
+        ref = 2 * ndi.map_coordinates(rc[c], np.stack([z, y, x]), order=1, mode="nearest")
+        np.testing.assert_allclose(up[c], ref, atol=1e-12)
+    const = np.full((3, 4, 4, 4), 1.25)
+    assert np.allclose(oracle.upsample_field(const, (8, 8, 8)), 2.5, atol=0)
+
+
+# --------------------------------------------------------------------------
+# invariants of the whole iteration
+# --------------------------------------------------------------------------
+
+def test_identical_images_give_zero_update():
+    """S = CT: Delta HU = 0, a = 1, b = 0, I'_s = CT, u = 0, r stays 0 exactly."""
+    c = make_case("c1")
+    ct = c.ct.astype(np.float64)
+    p = oracle.make_params(patch=(5, 5, 5), sigma=1.5, levels=2, iters=(3, 3))
+    r, f = oracle.register(ct, ct, p)
+    assert np.all(r == 0.0)
+    assert np.array_equal(f, ct)
+
+
+@pytest.mark.parametrize("kind", ["noise", "labels"])
+def test_affine_cbct_is_corrected_back(kind):
+    """S = alpha CT + beta inside every patch: I'_s = CT (a = 1/alpha), the
+    force vanishes and r stays exactly 0. Images with no near-flat patches:
+    textured noise, or a label image with values at least 50 HU apart."""
+    g = rng(17)
+    shape = (12, 13, 14)
+    if kind == "noise":
+        ct = g.normal(size=shape) * 200 + 30
+    else:
+        ct = g.choice([-1000.0, -50.0, 0.0, 60.0, 700.0, 1300.0], size=shape)
+        ct = ndi.zoom(ct, 1, order=0)
+    for alpha, beta in [(0.8, 120.0), (1.3, -250.0)]:
+        s = alpha * ct + beta
+        p = oracle.make_params(patch=(3, 3, 3), sigma=1.5, levels=1, iters=(4,))
+        r, f = oracle.register(ct, s, p)
+        assert np.all(r == 0.0)
+        np.testing.assert_allclose(f, ct, atol=1e-9 * 1500)
+
+
+def test_known_translation():
+    """CBCT(x) = CT(x + t) for a smooth analytic image (sign and limit).
+    (i) one iteration moves r towards t; (ii) r = t is a fixed point of DISC;
+    (iii) the warp/force/Gaussian composition without correction (plain
+    demons) converges to t; (iv) DISC from r = 0 removes most of the shift
+    (moment matching absorbs part of a translation of a locally near-affine
+    image, so the DISC limit from zero is only approached)."""
+    t = np.array([0.7, -0.4, 0.3])
+    shape = (48, 48, 48)
+    ct, cb = smooth_blob_pair(shape, tuple(t))
+    ct = ct.astype(np.float64)
+    cb = cb.astype(np.float64)
+    gm = np.sqrt(sum(q ** 2 for q in np.gradient(ct)))
+    mask = gm > np.percentile(gm, 70)
+    med = lambda r: np.array([np.median(r[c][mask]) for c in range(3)])  # noqa: E731
+
+    p1 = oracle.make_params(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(1,))
+    r1, _ = oracle.register(ct, cb, p1)
+    assert float(np.sum([r1[c][mask].mean() * t[c] for c in range(3)])) > 0
+
+    r0 = np.stack([np.full(shape, v) for v in t])
+    rfix, _, _, _ = oracle.iterate(ct, cb, r0, oracle.make_params(patch=(5, 5, 5), sigma=1.5), n=20)
+    assert np.abs(med(rfix) - t).max() < 0.02
+
+    r = np.zeros((3,) + shape)
+    for _ in range(50):
+        m = oracle.warp(ct, r)
+        r = r - oracle.force(m, cb)
+        r = np.stack([oracle.gauss(r[c], 1.5) for c in range(3)])
+    assert np.abs(med(r) - t).max() < 0.05
+
+    p = oracle.make_params(patch=(7, 7, 7), sigma=1.5, levels=2, iters=(50, 50))
+    rd, _ = oracle.register(ct, cb, p)
+    assert np.linalg.norm(med(rd) - t) < 0.25 * np.linalg.norm(t)
+
+
+def test_literal_iteration_matches_oracle():
+    """An independent composition of library routines (map_coordinates,
+    uniform_filter, clipped central differences, gaussian_filter) equals
+    three oracle iterations on a 12^3 volume."""
+    g = rng(18)
+    shape = (12, 12, 12)
+    ct = g.normal(size=shape) * 300
+    s = 0.9 * ndi.shift(ct, (0.3, -0.6, 0.8), order=1, mode="nearest") + 40 + g.normal(size=shape) * 10
+    patch, sigma, tau, eps = (3, 5, 3), 1.5, 1e-2, 1e-3
+    size = (patch[2], patch[1], patch[0])
+    R = int(np.ceil(3 * sigma))
+
+    def box(v):
+        mu = ndi.uniform_filter(v, size=size, mode="nearest")
+        return mu, ndi.uniform_filter(v * v, size=size, mode="nearest") - mu * mu
+
+    mu_s, var_s = box(s)
+    r = np.zeros((3,) + shape)
+    z, y, x = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    for _ in range(3):
+        m = ndi.map_coordinates(ct, np.stack([z + r[2], y + r[1], x + r[0]]), order=1, mode="nearest")
+        mu_m, var_m = box(m)
+        a = np.where(var_s > tau, np.sqrt(np.maximum(var_m, 0) / var_s), 1.0)
+        f = a * s + (mu_m - a * mu_s)
+        grads = []
+        for ax in (2, 1, 0):
+            n = shape[ax]
+            up = np.take(f, np.clip(np.arange(n) + 1, 0, n - 1), axis=ax)
+            dn = np.take(f, np.clip(np.arange(n) - 1, 0, n - 1), axis=ax)
+            grads.append((up - dn) / 2)
+        d = m - f
+        den = grads[0] ** 2 + grads[1] ** 2 + grads[2] ** 2 + d * d
+        ok = (den > 0) & (np.abs(d) >= eps)
+        u = np.stack([np.where(ok, d * gq / np.where(den > 0, den, 1), 0.0) for gq in grads])
+        rt = r - u
+        r = np.stack([ndi.gaussian_filter(rt[c], sigma, mode="nearest", radius=R) for c in range(3)])
+    ro, mo, fo, _ = oracle.iterate(ct, s, np.zeros((3,) + shape), oracle.make_params(patch=patch, sigma=sigma), n=3)
+    np.testing.assert_allclose(mo, m, atol=1e-9)
+    np.testing.assert_allclose(fo, f, atol=1e-8)
+    np.testing.assert_allclose(ro, r, atol=1e-9)
+
+
+def test_point_evaluators_agree_with_whole_volume():
+    """The *_pts functions (FP32 inputs) equal the whole-volume oracle steps."""
+    g = rng(19)
+    shape = (9, 10, 11)
+    ct = (g.normal(size=shape) * 300).astype(np.float32)
+    s = (g.normal(size=shape) * 300).astype(np.float32)
+    r = g.uniform(-2, 2, size=(3,) + shape).astype(np.float32)
+    pts = g.choice(ct.size, 60, replace=False)
+    m = oracle.warp(ct, r)
+    np.testing.assert_allclose(oracle.warp_pts(ct, r, pts), m.ravel()[pts], rtol=1e-14, atol=1e-12)
+    m32 = m.astype(np.float32)
+    patch = (3, 5, 7)
+    mu_m, var_m = oracle.patch_moments(m32, patch)
+    mu_s, var_s = oracle.patch_moments(s, patch)
+    _, _, f = oracle.correct(mu_m, var_m, mu_s, var_s, s)
+    np.testing.assert_allclose(oracle.correct_pts(m32, s, patch, pts), f.ravel()[pts], rtol=1e-12, atol=1e-9)
+    f32 = f.astype(np.float32)
+    u = oracle.force(m32, f32)
+    rt = r.astype(np.float64) - u
+    got = oracle.force_pts(m32, f32, r, pts)
+    for c in range(3):
+        np.testing.assert_allclose(got[:, c], rt[c].ravel()[pts], rtol=1e-13, atol=1e-13)
+    rt32 = rt.astype(np.float32)
+    gs = np.stack([oracle.gauss(rt32[c], 1.5) for c in range(3)])
+    got = oracle.gauss_pts(rt32, 1.5, pts)
+    for c in range(3):
+        np.testing.assert_allclose(got[:, c], gs[c].ravel()[pts], atol=1e-12)
