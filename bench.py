@@ -1,0 +1,199 @@
+"""DISC throughput on one MI355X: voxel-iterations/s of whole registrations.
+
+A step is one full DISC registration of the 256 x 256 x 96 head-and-neck
+phantom pair (patch 11^3, sigma 2, 3-level pyramid x 100 iterations):
+set-up (global shift, pyramid, static patch moments) plus every iteration
+and level switch, with the inputs already resident in HBM. The value counts
+the voxel-iterations of all levels (sum_l N_l K_l) per second of step time.
+
+Besides the JSON line on stdout, the run reports per-kernel HIP-event timing
+of the same timed steps (roofline of the dominant kernel against the 8 TB/s
+HBM peak) and the FP64 CPU oracle timed on a bounded sample of the same
+workload (cpu_baseline). Progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per voxel of each kernel launch (reads + writes of
+# its inputs and outputs once; gathers and halos counted once).
+BYTES_PER_VOXEL = {
+    "warp": 20.0,      # r 12 + CT 4 + m 4
+    "correct": 12.0,   # m 4 + ys 4 + f 4
+    "force": 32.0,     # m 4 + f 4 + r 12 + r~ 12
+    "smooth": 24.0,    # r~ 12 + r 12
+    "upsample": 13.5,  # fine r 12 + coarse r 12/8, per fine voxel
+}
+ALGORITHMIC_MIN_BYTES = 32.0  # read CT, CBCT, r; write r (whole iteration)
+
+WORKLOADS = {
+    "hn256x256x96": dict(case="c2"),
+    "hn512x512x160": dict(case="c3"),
+    "ellipsoid48": dict(case="c1"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(case, params, budget_s=20.0, max_iters=3):
+    """FP64 oracle on the finest level of the same pair: as many iterations as
+    fit in about budget_s (at least one). Static patch moments are computed
+    beforehand and not timed (the GPU computes them once per registration)."""
+    import numpy as np
+
+    import oracle
+
+    ct = case.ct.astype(np.float64)
+    _, s = oracle.global_shift(ct, case.cbct.astype(np.float64))
+    p = oracle.make_params(patch=params["patch"], sigma=params["sigma"], levels=1,
+                           iters=(1,))
+    mu_s, var_s = oracle.patch_moments(s, params["patch"])
+    r = np.zeros((3,) + ct.shape)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        r, _, _, _ = oracle.iterate(ct, s, r, p, n=1, mu_s=mu_s, var_s=var_s)
+        n += 1
+        el = time.perf_counter() - t0
+        log("  oracle iteration %d: %.1f s" % (n, el))
+        if n >= max_iters or el * (n + 1) / n > budget_s:
+            break
+    vox = float(ct.size) * n
+    return {
+        "value": vox / el,
+        "unit": "voxel-iterations/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": "%d finest-level iteration(s) of the %dx%dx%d pair from r = 0, patch %s, sigma %g (%.1f s)"
+                  % (n, ct.shape[2], ct.shape[1], ct.shape[0], "x".join(map(str, params["patch"])),
+                     params["sigma"], el),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="hn256x256x96", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel events in the timed steps")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs DISC on a single MI355X "
+              "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("RANK", "0")) != 0:
+        return
+
+    import torch
+
+    import paper_1204_6295_amd as disc
+    from synth.phantom import CONFIGS, make_case
+
+    dev = torch.device("cuda:0")
+    cname = WORKLOADS[args.workload]["case"]
+    cfg = CONFIGS[cname]
+    log("generating %s phantom pair %s" % (args.workload, cfg["shape"]))
+    case = make_case(cname, device="cuda")
+    ct = torch.from_numpy(case.ct).to(dev)
+    cb = torch.from_numpy(case.cbct).to(dev)
+    params = dict(patch=cfg["patch"], sigma=cfg["sigma"], levels=cfg["levels"], iters=cfg["iters"])
+    reg = disc.Registration(**params)
+
+    def step():
+        reg.set_volumes(ct, cb)
+        reg.run()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    launches_per_step = 4 * sum(cfg["iters"]) + (cfg["levels"] - 1)
+    if not args.no_timing:
+        reg.timing_enable(launches_per_step * args.steps + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1000.0 / args.steps
+    log("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step))
+
+    # voxel-iterations per step over all levels
+    dims = [tuple(cfg["shape"])]
+    for _ in range(cfg["levels"] - 1):
+        nz, ny, nx = dims[0]
+        dims.insert(0, ((nz + 1) // 2, (ny + 1) // 2, (nx + 1) // 2))
+    vox_it = sum(float(d[0] * d[1] * d[2]) * k for d, k in zip(dims, cfg["iters"]))
+    value = vox_it * args.steps / wall
+
+    roofline = None
+    kernels = {}
+    if not args.no_timing:
+        for name in disc.KERNELS:
+            n, ms, vox = reg.timing_read(name)
+            if n:
+                kernels[name] = dict(launches=n, total_ms=ms, avg_us=1000.0 * ms / n,
+                                     gbs=BYTES_PER_VOXEL[name] * vox / (ms * 1e-3) / 1e9)
+        dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+        k = kernels[dom]
+        n, ms, vox = reg.timing_read(dom)
+        achieved = BYTES_PER_VOXEL[dom] * vox / n / (ms / n * 1e-3) / 1e9
+        roofline = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": dom, "avg_launch_us": round(k["avg_us"], 2), "launches": n,
+            "bytes_per_voxel": BYTES_PER_VOXEL[dom],
+        }
+        for name, kk in kernels.items():
+            log("  %-9s launches %5d  avg %8.2f us  %7.1f GB/s  share %.1f%%" % (
+                name, kk["launches"], kk["avg_us"], kk["gbs"],
+                100.0 * kk["total_ms"] / sum(q["total_ms"] for q in kernels.values())))
+
+    out = {
+        "metric": "DISC voxel-iterations/s (whole registration, all pyramid levels)",
+        "value": round(value, 1),
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "shape_zyx": list(cfg["shape"]),
+            "patch": list(cfg["patch"]),
+            "sigma": cfg["sigma"],
+            "levels": cfg["levels"],
+            "iters_per_level": list(cfg["iters"]),
+            "voxel_iterations_per_step": vox_it,
+            "effective_hbm_frac_at_32B": round(ALGORITHMIC_MIN_BYTES * value / (HBM_PEAK_GBS * 1e9), 4),
+            "kernels": {k: {q: round(v, 3) for q, v in kk.items()} for k, kk in kernels.items()},
+        },
+    }
+    if roofline is not None:
+        out["roofline"] = roofline
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(case, params)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

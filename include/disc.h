@@ -1,0 +1,195 @@
+/*
+ * disc.h -- C ABI of libdisc, the MI355X (gfx950) implementation of the DISC
+ * iteration: demons registration of a planning CT onto a cone-beam CT with a
+ * simultaneous local intensity correction of the CBCT.
+ *
+ * Method: Zhen, Gu, Yan, Zhou, Jia, Jiang, "CT to Cone-beam CT Deformable
+ * Registration With Simultaneous Intensity Correction" (arXiv 1204.6295).
+ *   - registration model I_m(x + v(x)) = I_s(x), CT moving, CBCT static:
+ *     Sec. 2.1 and the first paragraph of Sec. 2.2;
+ *   - local linear correction I'_s = a I_s + b by matching the first two
+ *     patch moments: Sec. 2.2, Eq. 2-6, Appendix A.1-A.7;
+ *   - demons force: Sec. 2.1, Eq. 1 (static-gradient term, on I'_s);
+ *   - global shift, multi-scale pyramid and the per-level loop:
+ *     Sec. 2.3 and Algorithm A1 (fixed iteration counts per level).
+ *
+ * Conventions shared by every entry point
+ *   Layout.   A volume is float32 [nz][ny][nx], x contiguous, no padding.
+ *             A field is float32 [3][nz][ny][nx], components (x, y, z), in
+ *             voxel units of its level. m(x) = CT(x + r(x)).
+ *   Memory.   Every pointer argument named *_dev is device memory owned by
+ *             the caller. The library never allocates device memory: the
+ *             context works inside a caller-provided workspace.
+ *   Streams.  `stream` is a hipStream_t (NULL = default stream). All device
+ *             work is enqueued on it without host synchronisation; results
+ *             are valid once the caller has synchronised that stream.
+ *   Errors.   Every call returns a disc_status. Argument errors are found on
+ *             the host before any device work is enqueued. HIP launch errors
+ *             map to DISC_EHIP. disc_last_error() describes the last failure
+ *             (per context, or per thread for the context-free calls).
+ *   Threads.  A context is not thread-safe; use one context per stream.
+ *   Sizes.    nx, ny, nz >= 1; nx * ny * nz < 2^31. Patch extents are odd,
+ *             1 <= px, py <= 31 and 1 <= pz <= 15. Gaussian sigma in
+ *             (0, 8/3] voxels (at most 17 taps).
+ */
+#ifndef DISC_H
+#define DISC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DISC_MAX_LEVELS 8
+
+typedef struct disc_ctx disc_ctx;
+
+typedef enum {
+    DISC_OK = 0,
+    DISC_EINVAL = -1,   /* invalid argument (null pointer, bad size, bad parameter) */
+    DISC_ENOMEM = -2,   /* workspace smaller than disc_workspace_bytes() */
+    DISC_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
+    DISC_ESTATE = -4,   /* call out of order (e.g. iterate before set_volumes) */
+    DISC_ENOTSUP = -5   /* valid request outside what this build supports */
+} disc_status;
+
+typedef struct {
+    int   patch[3];      /* odd patch extents (px, py, pz): the n-voxel patches M, S of Eq. 3 */
+    float sigma;         /* Gaussian regularisation of r (Algorithm A1 step 6), voxels */
+    int   levels;        /* pyramid levels, 2x per level (Sec. 2.3), 1..DISC_MAX_LEVELS */
+    int   iters[DISC_MAX_LEVELS]; /* iterations per level, coarsest first */
+    int   global_shift;  /* 1: add mean(CT) - mean(CBCT) to the CBCT first (Sec. 2.3) */
+    float var_floor;     /* tau (HU^2): a static patch with variance <= tau is flat and
+                            only its mean is matched (a = 1) */
+    float diff_floor;    /* eps_d (HU): |m - I'_s| < eps_d gives a zero force */
+} disc_params;
+
+/* Defaults: patch 11^3, sigma 2, 3 levels x 100 iterations, global shift on,
+ * tau = 1e-2 HU^2, eps_d = 1e-3 HU. */
+int disc_params_default(disc_params* p);
+
+/* Validates *p and creates a host-side context. Does not touch the GPU.
+ * *out receives the context (NULL on error). */
+int disc_create(const disc_params* p, disc_ctx** out);
+
+/* Releases the context (host memory only). NULL is accepted. */
+void disc_destroy(disc_ctx* c);
+
+/* Message of the last failing call on c (or on this thread when c is NULL).
+ * The string stays valid until the next call that fails. */
+const char* disc_last_error(const disc_ctx* c);
+
+/* Bytes of device workspace disc_set_volumes needs for these parameters and
+ * finest-level dims; 0 if the arguments are invalid. */
+size_t disc_workspace_bytes(const disc_params* p, int nx, int ny, int nz);
+
+/* Algorithm A1 set-up (Sec. 2.3): global intensity shift of the CBCT, 2x2x2
+ * block-mean pyramid of CT and CBCT, patch moments of the static image per
+ * level (fixed for the whole run, Sec. 2.2 corrects the original I_s), and
+ * r := 0 at the coarsest level. ct_dev is borrowed (read every iteration at
+ * the finest level) until the next set_volumes or destroy; cbct_dev is only
+ * read by this call. workspace_dev (256-byte aligned) is borrowed likewise. */
+int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev,
+                     int nx, int ny, int nz, void* workspace_dev,
+                     size_t workspace_bytes, void* stream);
+
+/* Enqueues n DISC iterations (Algorithm A1 steps 1, 3-6): warp, patch
+ * moments, correction, force, update, Gaussian. When the current level has
+ * done its iters[] count and a finer level exists, the field is first
+ * up-sampled (Algorithm A1, last step) and the next level starts. After the
+ * finest level's count, further iterations stay at the finest level. */
+int disc_iterate(disc_ctx* c, int n, void* stream);
+
+/* Enqueues every iteration left in the schedule. */
+int disc_run(disc_ctx* c, void* stream);
+
+/* Current state: level index (0 = coarsest), iterations done at that level,
+ * and the level's dims (nx, ny, nz). Any output pointer may be NULL. */
+int disc_state(const disc_ctx* c, int* level, int* iter_in_level, int dims[3]);
+
+/* Copies the current field r ([3][nz][ny][nx] at the current level's dims)
+ * to out_dev; dims_out (host, may be NULL) receives (nx, ny, nz). */
+int disc_get_field(disc_ctx* c, float* out_dev, int dims_out[3], void* stream);
+
+/* Replaces the current field with r_dev (current level's dims). For resume
+ * from a saved field and for tests that start from a given field. */
+int disc_set_field(disc_ctx* c, const float* r_dev, void* stream);
+
+/* Copies I'_s = a I_s + b of the most recent iteration at the current level
+ * (Sec. 2.2; the corrected CBCT, Sec. 4) to out_dev [nz][ny][nx].
+ * DISC_ESTATE before the first iteration of the current level. */
+int disc_get_corrected(disc_ctx* c, float* out_dev, void* stream);
+
+/* ---- single steps, running the same kernels as disc_iterate ------------ */
+/* All buffers are caller-owned device memory of the stated sizes; inputs
+ * and outputs must not overlap. N = nx * ny * nz. */
+
+/* Sec. 2.1 model: m(x) = trilinear(ct, x + r(x)), corner indices clamped.
+ * ct, m: N floats; r: 3N floats. */
+int disc_step_warp(const float* ct_dev, const float* r_dev, int nx, int ny, int nz,
+                   float* m_dev, void* stream);
+
+/* Patch moments of the static image s (Eq. 3) folded into its standardised
+ * form ys = (s - E(S)) / STD(S), or s - E(S) on flat patches (var <= tau,
+ * flagged in the lowest mantissa bit). Library-internal encoding consumed
+ * by disc_step_correct. s, ys: N floats. */
+int disc_step_static_stats(const float* s_dev, int nx, int ny, int nz, const int patch[3],
+                           float var_floor, float* ys_dev, void* stream);
+
+/* Eq. 3-6 and I'_s = a I_s + b: patch mean/variance of m, a = STD(M)/STD(S),
+ * b = E(M) - a E(S), written as f = E(M) + STD(M) ys (flat static patch:
+ * f = E(M) + ys). m, ys, f: N floats. */
+int disc_step_correct(const float* m_dev, const float* ys_dev, int nx, int ny, int nz,
+                      const int patch[3], float* f_dev, void* stream);
+
+/* Eq. 1 static-gradient term on f = I'_s and the A1 step-5 update:
+ * rt = r - (m - f) grad f / (|grad f|^2 + (m - f)^2), zero where
+ * |m - f| < diff_floor. m, f: N floats; r, rt: 3N floats. */
+int disc_step_force(const float* m_dev, const float* f_dev, const float* r_dev,
+                    int nx, int ny, int nz, float diff_floor, float* rt_dev, void* stream);
+
+/* Algorithm A1 step 6: separable Gaussian of each field component, taps
+ * exp(-k^2 / 2 sigma^2) for |k| <= ceil(3 sigma), normalised, indices
+ * clamped. rt, r: 3N floats. */
+int disc_step_smooth(const float* rt_dev, int nx, int ny, int nz, float sigma,
+                     float* r_dev, void* stream);
+
+/* Sec. 2.3 global shift: s = cbct + (mean(ct) - mean(cbct)), means in FP64.
+ * dhu_dev (device, may be NULL) receives Delta HU as a double. scratch_dev
+ * must hold disc_step_shift_scratch_bytes() bytes. */
+size_t disc_step_shift_scratch_bytes(void);
+int disc_step_shift(const float* ct_dev, const float* cbct_dev, long n, float* s_dev,
+                    double* dhu_dev, void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* Sec. 2.3 multi-scale strategy: 2x2x2 block mean, indices clamped; out has
+ * dims (ceil(nx/2), ceil(ny/2), ceil(nz/2)). */
+int disc_step_downsample(const float* in_dev, int nx, int ny, int nz, float* out_dev,
+                         void* stream);
+
+/* Algorithm A1, last step: r_f(x) = 2 trilinear(r_c, (x + 1/2)/2 - 1/2),
+ * edge clamped, per component. rc: 3 * cnx*cny*cnz; rf: 3 * fnx*fny*fnz. */
+int disc_step_upsample_field(const float* rc_dev, int cnx, int cny, int cnz,
+                             float* rf_dev, int fnx, int fny, int fnz, void* stream);
+
+/* ---- measurement helpers ------------------------------------------------ */
+
+/* Plain device copy of `bytes` bytes (16-byte aligned pointers), used to
+ * calibrate hardware byte counters against a kernel of known traffic. */
+int disc_copy_kernel(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
+
+/* Per-kernel timing with HIP events on the launch stream. While enabled,
+ * every kernel disc_iterate launches is bracketed by an event pair; the
+ * library keeps at most max_records pairs. disc_timing_read synchronises
+ * the recorded events and returns, for kernel id k (0 warp, 1 correct,
+ * 2 force, 3 smooth, 4 upsample), the number of launches, their total
+ * milliseconds and the total voxels they processed. Re-enabling (any
+ * max_records, 0 = off) clears the records. */
+int disc_timing_enable(disc_ctx* c, int max_records);
+int disc_timing_read(disc_ctx* c, int kernel_id, int* launches, double* total_ms,
+                     double* total_voxels);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -73,6 +73,8 @@ def lib():
         if not os.path.exists(_SO):
             build()
         L = ctypes.CDLL(_SO)
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_threads.argtypes = []
         L.orc_mean.restype = ctypes.c_double
         L.orc_mean.argtypes = [_D, ctypes.c_long]
         L.orc_global_shift.restype = ctypes.c_double
@@ -110,6 +112,10 @@ def _f(a):
 def _dims(v):
     nz, ny, nx = v.shape[-3:]
     return int(nx), int(ny), int(nz)
+
+
+def threads():
+    return int(lib().orc_threads())
 
 
 def mean(v):

@@ -33,8 +33,14 @@
 #include "disc_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+int orc_threads(void)
+{
+    return omp_get_max_threads();
+}
 
 static int clampi(int v, int n)
 {

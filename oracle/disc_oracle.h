@@ -37,6 +37,9 @@ typedef struct {
     double diff_floor;   /* eps_d: |m - f'| < eps_d gives a zero force */
 } orc_params;
 
+/* Number of OpenMP threads the whole-volume functions use. */
+int orc_threads(void);
+
 /* Sec. 2.3: plain mean over all voxels. */
 double orc_mean(const double* v, long n);
 

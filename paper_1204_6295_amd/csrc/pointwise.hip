@@ -1,0 +1,315 @@
+// Per-voxel DISC kernels for gfx950: the trilinear warp of the CT, the Eq. 1
+// force with the field update, and the set-up / level-switch kernels
+// (global shift reduction, 2x2x2 pyramid, field up-sampling).
+//
+// All of these are HBM-streaming kernels: one thread per voxel, x mapped to
+// the 64 lanes of a wave so every plain load and store is a contiguous
+// 256-byte wave access; gathers (warp corners, gradient neighbours) hit the
+// same or adjacent cache lines.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace disc {
+
+namespace {
+
+constexpr int BX = 64;  // one wave along x
+constexpr int BY = 4;   // four waves along y
+
+inline dim3 grid_for(Dims d)
+{
+    return dim3((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz);
+}
+
+// Keeps float->int conversions in range for any input (NaN/Inf included);
+// the clamped voxel index then always lies inside the volume.
+__device__ inline int floor_to_int(float v)
+{
+    float f = floorf(v);
+    f = fminf(fmaxf(f, -1048576.0f), 1048576.0f);
+    return (int)f;
+}
+
+// Sec. 2.1 model I_m(x + v(x)) = I_s(x): the deformed moving image at x is the
+// CT sampled at x + r(x). The weights come from the fractional part of r
+// alone and the integer voxel is added separately, so FP32 keeps the full
+// sub-voxel resolution at any volume size.
+__global__ __launch_bounds__(BX * BY) void k_warp(const float* __restrict__ ct,
+                                                 const float* __restrict__ r,
+                                                 float* __restrict__ m, int nx, int ny, int nz)
+{
+    const int x = blockIdx.x * BX + threadIdx.x;
+    const int y = blockIdx.y * BY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx || y >= ny) return;
+    const long N = (long)nx * ny * nz;
+    const long i = ((long)z * ny + y) * nx + x;
+    const float rx = r[i], ry = r[N + i], rz = r[2 * N + i];
+    const float tx = rx - floorf(rx), ty = ry - floorf(ry), tz = rz - floorf(rz);
+    const int ix = x + floor_to_int(rx), iy = y + floor_to_int(ry), iz = z + floor_to_int(rz);
+    const int x0 = clampi(ix, nx), x1 = clampi(ix + 1, nx);
+    const int y0 = clampi(iy, ny), y1 = clampi(iy + 1, ny);
+    const int z0 = clampi(iz, nz), z1 = clampi(iz + 1, nz);
+    const float* p00 = ct + ((long)z0 * ny + y0) * nx;
+    const float* p01 = ct + ((long)z0 * ny + y1) * nx;
+    const float* p10 = ct + ((long)z1 * ny + y0) * nx;
+    const float* p11 = ct + ((long)z1 * ny + y1) * nx;
+    const float c00 = fmaf(tx, p00[x1] - p00[x0], p00[x0]);
+    const float c01 = fmaf(tx, p01[x1] - p01[x0], p01[x0]);
+    const float c10 = fmaf(tx, p10[x1] - p10[x0], p10[x0]);
+    const float c11 = fmaf(tx, p11[x1] - p11[x0], p11[x0]);
+    const float c0 = fmaf(ty, c01 - c00, c00);
+    const float c1 = fmaf(ty, c11 - c10, c10);
+    m[i] = fmaf(tz, c1 - c0, c0);
+}
+
+// Eq. 1, static-gradient term, evaluated on the corrected static image
+// f = I'_s, followed by the Algorithm A1 step-5 update. Under m(x) = CT(x + r)
+// adding the increment is r - u. Central differences with clamped neighbours.
+__global__ __launch_bounds__(BX * BY) void k_force(const float* __restrict__ m,
+                                                  const float* __restrict__ f,
+                                                  const float* __restrict__ r,
+                                                  float* __restrict__ rt, int nx, int ny, int nz,
+                                                  float eps_d)
+{
+    const int x = blockIdx.x * BX + threadIdx.x;
+    const int y = blockIdx.y * BY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx || y >= ny) return;
+    const long plane = (long)nx * ny;
+    const long N = plane * nz;
+    const long i = (long)z * plane + (long)y * nx + x;
+    const float fc = f[i];
+    const float gx = (f[i + (x < nx - 1 ? 1 : 0)] - f[i - (x > 0 ? 1 : 0)]) * 0.5f;
+    const float gy = (f[i + (y < ny - 1 ? nx : 0)] - f[i - (y > 0 ? nx : 0)]) * 0.5f;
+    const float gz = (f[i + (z < nz - 1 ? plane : 0)] - f[i - (z > 0 ? plane : 0)]) * 0.5f;
+    const float d = m[i] - fc;
+    const float den = gx * gx + gy * gy + gz * gz + d * d;
+    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+    if (den > 0.0f && fabsf(d) >= eps_d) {
+        const float s = d / den;
+        ux = s * gx;
+        uy = s * gy;
+        uz = s * gz;
+    }
+    rt[i] = r[i] - ux;
+    rt[N + i] = r[N + i] - uy;
+    rt[2 * N + i] = r[2 * N + i] - uz;
+}
+
+// Sec. 2.3 multi-scale strategy: 2x2x2 block mean, clamped at odd edges.
+__global__ __launch_bounds__(BX * BY) void k_downsample(const float* __restrict__ in,
+                                                       float* __restrict__ out, int nx, int ny,
+                                                       int nz, int cx, int cy)
+{
+    const int x = blockIdx.x * BX + threadIdx.x;
+    const int y = blockIdx.y * BY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= cx || y >= cy) return;
+    float s = 0.0f;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const float* row =
+                in + ((long)clampi(2 * z + dz, nz) * ny + clampi(2 * y + dy, ny)) * nx;
+            s += row[clampi(2 * x, nx)] + row[clampi(2 * x + 1, nx)];
+        }
+    out[((long)z * cy + y) * cx + x] = s * 0.125f;
+}
+
+// Algorithm A1, last step: coarse field sampled at the cell-centred position
+// (x + 1/2)/2 - 1/2 = x/2 - 1/4 and doubled (one coarse voxel = two fine).
+__global__ __launch_bounds__(BX * BY) void k_upsample(const float* __restrict__ rc,
+                                                     float* __restrict__ rf, int cnx, int cny,
+                                                     int cnz, int fnx, int fny, int fnz)
+{
+    const int x = blockIdx.x * BX + threadIdx.x;
+    const int y = blockIdx.y * BY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= fnx || y >= fny) return;
+    const float px = 0.5f * x - 0.25f, py = 0.5f * y - 0.25f, pz = 0.5f * z - 0.25f;
+    const float fx = floorf(px), fy = floorf(py), fz = floorf(pz);
+    const float tx = px - fx, ty = py - fy, tz = pz - fz;
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    const int x0 = clampi(ix, cnx), x1 = clampi(ix + 1, cnx);
+    const int y0 = clampi(iy, cny), y1 = clampi(iy + 1, cny);
+    const int z0 = clampi(iz, cnz), z1 = clampi(iz + 1, cnz);
+    const long nc = (long)cnx * cny * cnz, nf = (long)fnx * fny * fnz;
+    const long o = ((long)z * fny + y) * fnx + x;
+    for (int c = 0; c < 3; ++c) {
+        const float* v = rc + c * nc;
+        const float* p00 = v + ((long)z0 * cny + y0) * cnx;
+        const float* p01 = v + ((long)z0 * cny + y1) * cnx;
+        const float* p10 = v + ((long)z1 * cny + y0) * cnx;
+        const float* p11 = v + ((long)z1 * cny + y1) * cnx;
+        const float c00 = fmaf(tx, p00[x1] - p00[x0], p00[x0]);
+        const float c01 = fmaf(tx, p01[x1] - p01[x0], p01[x0]);
+        const float c10 = fmaf(tx, p10[x1] - p10[x0], p10[x0]);
+        const float c11 = fmaf(tx, p11[x1] - p11[x0], p11[x0]);
+        const float c0 = fmaf(ty, c01 - c00, c00);
+        const float c1 = fmaf(ty, c11 - c10, c10);
+        rf[c * nf + o] = 2.0f * fmaf(tz, c1 - c0, c0);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, long n, float v)
+{
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src,
+                                              float4* __restrict__ dst, long n16)
+{
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n16; i += (long)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
+// Global shift, pass 1: FP64 partial sums of CT and CBCT per block, in a
+// fixed order (grid-stride, then a fixed LDS tree), so the result is
+// reproducible run to run.
+constexpr int kShiftBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_shift_partial(const float* __restrict__ ct,
+                                                       const float* __restrict__ cb, long n,
+                                                       double2* __restrict__ part)
+{
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kShiftBlocks * 256) {
+        a += (double)ct[i];
+        b += (double)cb[i];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sa[0], sb[0]);
+}
+
+// Pass 2 (one block): Delta HU = (sum CT - sum CBCT) / n.
+__global__ __launch_bounds__(256) void k_shift_finish(const double2* __restrict__ part, long n,
+                                                      double* __restrict__ dhu)
+{
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < kShiftBlocks; k += 256) {
+        a += part[k].x;
+        b += part[k].y;
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dhu[0] = (sa[0] - sb[0]) / (double)n;
+}
+
+// Pass 3: s = cbct + Delta HU, rounded once to FP32.
+__global__ __launch_bounds__(256) void k_shift_apply(const float* __restrict__ cb, long n,
+                                                     const double* __restrict__ dhu,
+                                                     float* __restrict__ s)
+{
+    const double d = dhu[0];
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+        s[i] = (float)((double)cb[i] + d);
+}
+
+inline unsigned blocks_for(long n, long per_block)
+{
+    long b = (n + per_block - 1) / per_block;
+    if (b > 65536) b = 65536;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+bool make_gauss_taps(float sigma, GaussTaps* t)
+{
+    if (!(sigma > 0.0f)) return false;
+    const double s = (double)sigma;
+    const int R = (int)std::ceil(3.0 * s);
+    if (R > kMaxGaussR) return false;
+    double w[2 * kMaxGaussR + 1];
+    double sum = 0.0;
+    for (int k = -R; k <= R; ++k) {
+        w[k + R] = std::exp(-(double)k * k / (2.0 * s * s));
+        sum += w[k + R];
+    }
+    t->R = R;
+    for (int k = 0; k < 2 * kMaxGaussR + 1; ++k) t->w[k] = k <= 2 * R ? (float)(w[k] / sum) : 0.0f;
+    return true;
+}
+
+hipError_t launch_warp(const float* ct, const float* r, float* m, Dims d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_warp, grid_for(d), dim3(BX, BY), 0, s, ct, r, m, d.nx, d.ny, d.nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(const float* m, const float* f, const float* r, float* rt, Dims d,
+                        float eps_d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_force, grid_for(d), dim3(BX, BY), 0, s, m, f, r, rt, d.nx, d.ny, d.nz,
+                       eps_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_downsample(const float* in, float* out, Dims d, hipStream_t s)
+{
+    Dims c{(d.nx + 1) / 2, (d.ny + 1) / 2, (d.nz + 1) / 2};
+    hipLaunchKernelGGL(k_downsample, grid_for(c), dim3(BX, BY), 0, s, in, out, d.nx, d.ny, d.nz,
+                       c.nx, c.ny);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample_field(const float* rc, Dims dc, float* rf, Dims df, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_upsample, grid_for(df), dim3(BX, BY), 0, s, rc, rf, dc.nx, dc.ny, dc.nz,
+                       df.nx, df.ny, df.nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, long n, float v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256 * 8)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
+{
+    const long n16 = (long)(bytes / 16);
+    hipLaunchKernelGGL(k_copy, dim3(blocks_for(n16, 256 * 4)), dim3(256), 0, s,
+                       (const float4*)src, (float4*)dst, n16);
+    return hipGetLastError();
+}
+
+size_t shift_scratch_bytes()
+{
+    return (size_t)kShiftBlocks * sizeof(double2) + 2 * sizeof(double);
+}
+
+hipError_t launch_shift(const float* ct, const float* cbct, long n, float* s, double* dhu,
+                        void* scratch, hipStream_t st)
+{
+    double2* part = (double2*)scratch;
+    double* d = dhu ? dhu : (double*)(part + kShiftBlocks);
+    hipLaunchKernelGGL(k_shift_partial, dim3(kShiftBlocks), dim3(256), 0, st, ct, cbct, n, part);
+    hipLaunchKernelGGL(k_shift_finish, dim3(1), dim3(256), 0, st, part, n, d);
+    hipLaunchKernelGGL(k_shift_apply, dim3(blocks_for(n, 256 * 8)), dim3(256), 0, st, cbct, n, d, s);
+    return hipGetLastError();
+}
+
+}  // namespace disc

@@ -1,0 +1,128 @@
+"""Whole-registration parity, invariants and the ABI state machine on the GPU.
+
+Final-field bar: per-voxel Euclidean error max <= 0.05 voxel and RMS <= 0.01
+voxel against the FP64 oracle running the same schedule on the same FP32
+inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import FIELD_MAX, FIELD_RMS, field_err, rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def disc():
+    import paper_1204_6295_amd as d
+
+    d.lib()
+    return d
+
+
+def run_gpu(disc, ct, cb, **kw):
+    reg = disc.Registration(**kw)
+    reg.set_volumes(to_dev(ct), to_dev(cb))
+    reg.run()
+    return reg, to_np(reg.field()), to_np(reg.corrected())
+
+
+def test_c1_matches_oracle(disc):
+    """48^3 ellipsoid phantom, patch 5^3, sigma 1.5, one level, 20 iterations."""
+    from synth.phantom import make_case
+
+    c = make_case("c1")
+    kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,))
+    reg, r, f = run_gpu(disc, c.ct, c.cbct, **kw)
+    r_ref, f_ref = oracle.register(c.ct, c.cbct, oracle.make_params(**kw))
+    emax, erms = field_err(r, r_ref)
+    print("c1 field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
+    assert emax <= FIELD_MAX and erms <= FIELD_RMS
+    assert rel_err(f, f_ref) <= 1e-3
+    assert np.abs(r_ref).max() > 0.5  # the registration actually moved
+
+
+@pytest.mark.parametrize("shape,patch,sigma,iters", [
+    ((24, 64, 64), (7, 7, 5), 2.0, (15, 15, 10)),
+    ((19, 45, 70), (11, 11, 11), 2.0, (10, 10, 5)),
+])
+def test_pyramid_matches_oracle(disc, shape, patch, sigma, iters):
+    """Head-and-neck phantom, 3-level pyramid with odd and even dims."""
+    from synth.phantom import make_hn_pair
+
+    c = make_hn_pair(shape, pair=1)
+    kw = dict(patch=patch, sigma=sigma, levels=3, iters=iters)
+    reg, r, f = run_gpu(disc, c.ct, c.cbct, **kw)
+    assert reg.state()[0] == 2 and reg.state()[2] == shape
+    r_ref, f_ref = oracle.register(c.ct, c.cbct, oracle.make_params(**kw))
+    emax, erms = field_err(r, r_ref)
+    print("pyramid field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
+    assert emax <= FIELD_MAX and erms <= FIELD_RMS
+    assert rel_err(f, f_ref) <= 1e-3
+
+
+def test_identical_images_zero_update(disc):
+    """S = CT: a = 1 (or mean-only on flat patches), I'_s = CT, u = 0: r stays
+    exactly zero through every level."""
+    from synth.phantom import make_case
+
+    c = make_case("c1")
+    _, r, f = run_gpu(disc, c.ct, c.ct, patch=(5, 5, 5), sigma=1.5, levels=2, iters=(3, 3))
+    assert np.all(r == 0.0)
+    assert rel_err(f, c.ct) <= 1e-6
+
+
+def test_affine_cbct_corrected_back(disc):
+    """S = alpha CT + beta on an image with no near-flat patches: I'_s = CT
+    and the field stays exactly zero."""
+    g = np.random.default_rng(5)
+    ct = (g.normal(size=(20, 24, 70)) * 200 + 30).astype(np.float32)
+    cb = (1.25 * ct.astype(np.float64) - 250.0).astype(np.float32)
+    _, r, f = run_gpu(disc, ct, cb, patch=(3, 3, 3), sigma=1.5, levels=1, iters=(4,))
+    assert np.all(r == 0.0)
+    assert rel_err(f, ct) <= 1e-5
+
+
+def test_deterministic(disc):
+    from synth.phantom import make_case
+
+    c = make_case("c1")
+    kw = dict(patch=(5, 5, 5), sigma=1.5, levels=2, iters=(5, 5))
+    _, r1, f1 = run_gpu(disc, c.ct, c.cbct, **kw)
+    _, r2, f2 = run_gpu(disc, c.ct, c.cbct, **kw)
+    assert np.array_equal(r1, r2) and np.array_equal(f1, f2)
+
+
+def test_state_machine_and_errors(disc):
+    import torch
+
+    from synth.phantom import make_case
+
+    c = make_case("c1")
+    reg = disc.Registration(patch=(5, 5, 5), sigma=1.5, levels=2, iters=(2, 3))
+    with pytest.raises(disc.DiscError) as e:
+        reg.iterate(1)
+    assert e.value.code == disc.DISC_ESTATE
+    reg.set_volumes(to_dev(c.ct), to_dev(c.cbct))
+    assert reg.state() == (0, 0, (24, 24, 24))
+    with pytest.raises(disc.DiscError) as e:
+        reg.corrected()
+    assert e.value.code == disc.DISC_ESTATE
+    reg.iterate(2)
+    assert reg.state() == (0, 2, (24, 24, 24))
+    reg.iterate(1)  # switches level first
+    assert reg.state() == (1, 1, (48, 48, 48))
+    reg.run()
+    assert reg.state() == (1, 3, (48, 48, 48))
+    reg.iterate(2)  # extra iterations stay at the finest level
+    assert reg.state() == (1, 5, (48, 48, 48))
+    # resume: a saved field, set back, continues identically
+    r_saved = reg.field()
+    reg.iterate(1)
+    r_a = to_np(reg.field())
+    reg.set_field(r_saved)
+    reg.iterate(1)
+    assert np.array_equal(to_np(reg.field()), r_a)
+    with pytest.raises(ValueError):
+        reg.set_field(torch.zeros((3, 4, 4, 4), device="cuda:0"))
