@@ -27,8 +27,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_VOXEL = {
     "warp": 20.0,      # r 12 + CT 4 + m 4
     "correct": 12.0,   # m 4 + ys 4 + f 4
-    "force": 32.0,     # m 4 + f 4 + r 12 + r~ 12
-    "smooth": 24.0,    # r~ 12 + r 12
+    "force_xy": 32.0,  # m 4 + f 4 + r 12 + xy-filtered r~ 12
+    "smooth_z": 24.0,  # xy-filtered r~ 12 + r 12
     "upsample": 13.5,  # fine r 12 + coarse r 12/8, per fine voxel
 }
 ALGORITHMIC_MIN_BYTES = 32.0  # read CT, CBCT, r; write r (whole iteration)
@@ -44,7 +44,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(case, params, budget_s=20.0, max_iters=3):
+def cpu_baseline(case, params, budget_s=20.0, max_iters=10):
     """FP64 oracle on the finest level of the same pair: as many iterations as
     fit in about budget_s (at least one). Static patch moments are computed
     beforehand and not timed (the GPU computes them once per registration)."""
@@ -161,6 +161,13 @@ def main():
             log("  %-9s launches %5d  avg %8.2f us  %7.1f GB/s  share %.1f%%" % (
                 name, kk["launches"], kk["avg_us"], kk["gbs"],
                 100.0 * kk["total_ms"] / sum(q["total_ms"] for q in kernels.values())))
+        for lv in range(cfg["levels"]):
+            parts = []
+            for name in disc.KERNELS:
+                n, ms, vox = reg.timing_read(name, lv)
+                if n:
+                    parts.append("%s %.1f us" % (name, 1000.0 * ms / n))
+            log("  level %d %s: %s" % (lv, "x".join(map(str, dims[lv][::-1])), ", ".join(parts)))
 
     out = {
         "metric": "DISC voxel-iterations/s (whole registration, all pyramid levels)",

@@ -143,17 +143,21 @@ int disc_step_static_stats(const float* s_dev, int nx, int ny, int nz, const int
 int disc_step_correct(const float* m_dev, const float* ys_dev, int nx, int ny, int nz,
                       const int patch[3], float* f_dev, void* stream);
 
-/* Eq. 1 static-gradient term on f = I'_s and the A1 step-5 update:
- * rt = r - (m - f) grad f / (|grad f|^2 + (m - f)^2), zero where
- * |m - f| < diff_floor. m, f: N floats; r, rt: 3N floats. */
-int disc_step_force(const float* m_dev, const float* f_dev, const float* r_dev,
-                    int nx, int ny, int nz, float diff_floor, float* rt_dev, void* stream);
+/* Eq. 1 static-gradient term on f = I'_s, the A1 step-5 update and the
+ * step-6 Gaussian: rt = r - (m - f) grad f / (|grad f|^2 + (m - f)^2), zero
+ * where |m - f| < diff_floor (central differences, clamped), then
+ * r_out = G_sigma * rt per component. q is 3N floats of scratch (the
+ * xy-filtered field); rt (may be NULL) receives r - u. m, f: N floats;
+ * r, r_out: 3N floats. */
+int disc_step_force_smooth(const float* m_dev, const float* f_dev, const float* r_dev,
+                           int nx, int ny, int nz, float sigma, float diff_floor,
+                           float* q_dev, float* r_out_dev, float* rt_dev, void* stream);
 
-/* Algorithm A1 step 6: separable Gaussian of each field component, taps
- * exp(-k^2 / 2 sigma^2) for |k| <= ceil(3 sigma), normalised, indices
- * clamped. rt, r: 3N floats. */
+/* Algorithm A1 step 6 alone: separable Gaussian of each field component,
+ * taps exp(-k^2 / 2 sigma^2) for |k| <= ceil(3 sigma), normalised, indices
+ * clamped. rt, q (scratch), r: 3N floats. */
 int disc_step_smooth(const float* rt_dev, int nx, int ny, int nz, float sigma,
-                     float* r_dev, void* stream);
+                     float* q_dev, float* r_dev, void* stream);
 
 /* Sec. 2.3 global shift: s = cbct + (mean(ct) - mean(cbct)), means in FP64.
  * dhu_dev (device, may be NULL) receives Delta HU as a double. scratch_dev
@@ -182,11 +186,12 @@ int disc_copy_kernel(const void* src_dev, void* dst_dev, size_t bytes, void* str
  * every kernel disc_iterate launches is bracketed by an event pair; the
  * library keeps at most max_records pairs. disc_timing_read synchronises
  * the recorded events and returns, for kernel id k (0 warp, 1 correct,
- * 2 force, 3 smooth, 4 upsample), the number of launches, their total
+ * 2 force + xy smoothing, 3 z smoothing, 4 upsample) at pyramid level
+ * `level` (-1 = all levels), the number of launches, their total
  * milliseconds and the total voxels they processed. Re-enabling (any
  * max_records, 0 = off) clears the records. */
 int disc_timing_enable(disc_ctx* c, int max_records);
-int disc_timing_read(disc_ctx* c, int kernel_id, int* launches, double* total_ms,
+int disc_timing_read(disc_ctx* c, int kernel_id, int level, int* launches, double* total_ms,
                      double* total_voxels);
 
 #ifdef __cplusplus

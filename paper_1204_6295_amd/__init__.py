@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libdisc.so")
 
 DISC_OK, DISC_EINVAL, DISC_ENOMEM, DISC_EHIP, DISC_ESTATE, DISC_ENOTSUP = 0, -1, -2, -3, -4, -5
 MAX_LEVELS = 8
-KERNELS = {"warp": 0, "correct": 1, "force": 2, "smooth": 3, "upsample": 4}
+KERNELS = {"warp": 0, "correct": 1, "force_xy": 2, "smooth_z": 3, "upsample": 4}
 
 _V = ctypes.c_void_p
 _I = ctypes.c_int
@@ -67,15 +67,15 @@ _SIGS = [
     ("disc_step_warp", _I, [_V, _V, _I, _I, _I, _V, _V]),
     ("disc_step_static_stats", _I, [_V, _I, _I, _I, _IP, _F, _V, _V]),
     ("disc_step_correct", _I, [_V, _V, _I, _I, _I, _IP, _V, _V]),
-    ("disc_step_force", _I, [_V, _V, _V, _I, _I, _I, _F, _V, _V]),
-    ("disc_step_smooth", _I, [_V, _I, _I, _I, _F, _V, _V]),
+    ("disc_step_force_smooth", _I, [_V, _V, _V, _I, _I, _I, _F, _F, _V, _V, _V, _V]),
+    ("disc_step_smooth", _I, [_V, _I, _I, _I, _F, _V, _V, _V]),
     ("disc_step_shift_scratch_bytes", ctypes.c_size_t, []),
     ("disc_step_shift", _I, [_V, _V, ctypes.c_long, _V, _V, _V, ctypes.c_size_t, _V]),
     ("disc_step_downsample", _I, [_V, _I, _I, _I, _V, _V]),
     ("disc_step_upsample_field", _I, [_V, _I, _I, _I, _V, _I, _I, _I, _V]),
     ("disc_copy_kernel", _I, [_V, _V, ctypes.c_size_t, _V]),
     ("disc_timing_enable", _I, [_V, _I]),
-    ("disc_timing_read", _I, [_V, _I, _IP, ctypes.POINTER(ctypes.c_double),
+    ("disc_timing_read", _I, [_V, _I, _I, _IP, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)]),
 ]
 
@@ -223,13 +223,14 @@ class Registration:
     def timing_enable(self, max_records):
         _check(lib().disc_timing_enable(self._h, int(max_records)), self._h)
 
-    def timing_read(self, kernel):
+    def timing_read(self, kernel, level=-1):
+        """(launches, total ms, total voxels) of one kernel, at one level or all (-1)."""
         kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         n = ctypes.c_int()
         ms = ctypes.c_double()
         vox = ctypes.c_double()
-        _check(lib().disc_timing_read(self._h, kid, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(vox)),
-               self._h)
+        _check(lib().disc_timing_read(self._h, kid, int(level), ctypes.byref(n), ctypes.byref(ms),
+                                      ctypes.byref(vox)), self._h)
         return n.value, ms.value, vox.value
 
 
@@ -263,20 +264,27 @@ def correct(m, ys, patch, stream=None):
     return f
 
 
-def force(m, f, r, diff_floor=1e-3, stream=None):
+def force_smooth(m, f, r, sigma, diff_floor=1e-3, want_rt=False, stream=None):
+    """Eq. 1 force, update and Gaussian. Returns r_out, or (r_out, r - u)."""
     nx, ny, nz = _vol_dims(m)
-    rt = torch.empty_like(r)
-    _check(lib().disc_step_force(_dev(m, name="m"), _dev(f, m.shape, "f"), _dev(r, (3,) + tuple(m.shape), "r"),
-                                 nx, ny, nz, float(diff_floor), _dev(rt), _stream(stream)))
-    return rt
+    q = torch.empty_like(r)
+    out = torch.empty_like(r)
+    rt = torch.empty_like(r) if want_rt else None
+    _check(lib().disc_step_force_smooth(_dev(m, name="m"), _dev(f, m.shape, "f"),
+                                        _dev(r, (3,) + tuple(m.shape), "r"), nx, ny, nz, float(sigma),
+                                        float(diff_floor), _dev(q), _dev(out),
+                                        _dev(rt) if want_rt else None, _stream(stream)))
+    return (out, rt) if want_rt else out
 
 
 def smooth(rt, sigma, stream=None):
     if rt.dim() != 4 or rt.shape[0] != 3:
         raise ValueError("field must have shape (3, nz, ny, nx)")
     nz, ny, nx = rt.shape[1:]
+    q = torch.empty_like(rt)
     r = torch.empty_like(rt)
-    _check(lib().disc_step_smooth(_dev(rt, name="rt"), nx, ny, nz, float(sigma), _dev(r), _stream(stream)))
+    _check(lib().disc_step_smooth(_dev(rt, name="rt"), nx, ny, nz, float(sigma), _dev(q), _dev(r),
+                                  _stream(stream)))
     return r
 
 

@@ -18,10 +18,11 @@ namespace {
 
 thread_local std::string g_thread_err;
 
-enum KernelId { K_WARP = 0, K_CORRECT = 1, K_FORCE = 2, K_SMOOTH = 3, K_UPSAMPLE = 4, K_COUNT = 5 };
+enum KernelId { K_WARP = 0, K_CORRECT = 1, K_FORCE_XY = 2, K_SMOOTH_Z = 3, K_UPSAMPLE = 4, K_COUNT = 5 };
 
 struct TimingRec {
     int kid;
+    int level;
     double voxels;
 };
 
@@ -166,11 +167,11 @@ struct Timed {
     disc_ctx* c;
     hipStream_t st;
     int slot = -1;
-    Timed(disc_ctx* cc, hipStream_t s, int kid, double vox) : c(cc), st(s)
+    Timed(disc_ctx* cc, hipStream_t s, int kid, int level, double vox) : c(cc), st(s)
     {
         if (c->max_rec > 0 && (int)c->rec.size() < c->max_rec) {
             slot = (int)c->rec.size();
-            c->rec.push_back(TimingRec{kid, vox});
+            c->rec.push_back(TimingRec{kid, level, vox});
             (void)hipEventRecord(c->ev[2 * slot], st);
         }
     }
@@ -186,7 +187,7 @@ int one_iteration(disc_ctx* c, hipStream_t st)
     if (c->it >= c->p.iters[c->level] && c->level < c->L - 1) {
         const Dims dc = c->dims[c->level], df = c->dims[c->level + 1];
         {
-            Timed tm(c, st, K_UPSAMPLE, (double)df.n());
+            Timed tm(c, st, K_UPSAMPLE, c->level + 1, (double)df.n());
             e = disc::launch_upsample_field(c->r[c->cur], dc, c->r[1 - c->cur], df, st);
         }
         if (e != hipSuccess) return hip_fail(c, e, "upsample_field");
@@ -199,27 +200,27 @@ int one_iteration(disc_ctx* c, hipStream_t st)
     const Dims d = c->dims[l];
     const double vox = (double)d.n();
     float* r = c->r[c->cur];
-    float* rt = c->r[1 - c->cur];
+    float* q = c->r[1 - c->cur];
     {
-        Timed tm(c, st, K_WARP, vox);
+        Timed tm(c, st, K_WARP, l, vox);
         e = disc::launch_warp(c->ct[l], r, c->m, d, st);
     }
     if (e != hipSuccess) return hip_fail(c, e, "warp");
     {
-        Timed tm(c, st, K_CORRECT, vox);
+        Timed tm(c, st, K_CORRECT, l, vox);
         e = disc::launch_correct(c->m, c->ys[l], c->f, d, c->p.patch, st);
     }
     if (e != hipSuccess) return hip_fail(c, e, "correct");
     {
-        Timed tm(c, st, K_FORCE, vox);
-        e = disc::launch_force(c->m, c->f, r, rt, d, c->p.diff_floor, st);
+        Timed tm(c, st, K_FORCE_XY, l, vox);
+        e = disc::launch_force_xy(c->m, c->f, r, q, nullptr, d, c->p.diff_floor, c->taps, st);
     }
-    if (e != hipSuccess) return hip_fail(c, e, "force");
+    if (e != hipSuccess) return hip_fail(c, e, "force + xy smoothing");
     {
-        Timed tm(c, st, K_SMOOTH, vox);
-        e = disc::launch_smooth(rt, r, d, c->taps, st);
+        Timed tm(c, st, K_SMOOTH_Z, l, vox);
+        e = disc::launch_smooth_z(q, r, d, c->taps, st);
     }
-    if (e != hipSuccess) return hip_fail(c, e, "smooth");
+    if (e != hipSuccess) return hip_fail(c, e, "z smoothing");
     c->it += 1;
     c->f_valid = true;
     return DISC_OK;
@@ -448,26 +449,34 @@ int disc_step_correct(const float* m_dev, const float* ys_dev, int nx, int ny, i
     return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "correct");
 }
 
-int disc_step_force(const float* m_dev, const float* f_dev, const float* r_dev, int nx, int ny,
-                    int nz, float diff_floor, float* rt_dev, void* stream)
+int disc_step_force_smooth(const float* m_dev, const float* f_dev, const float* r_dev, int nx,
+                           int ny, int nz, float sigma, float diff_floor, float* q_dev,
+                           float* r_out_dev, float* rt_dev, void* stream)
 {
-    if (!m_dev || !f_dev || !r_dev || !rt_dev) return fail(nullptr, DISC_EINVAL, "null pointer");
+    if (!m_dev || !f_dev || !r_dev || !q_dev || !r_out_dev)
+        return fail(nullptr, DISC_EINVAL, "null pointer");
     DISC_CHECK_DIMS(nx, ny, nz);
     if (!(diff_floor >= 0.0f) || !std::isfinite(diff_floor))
         return fail(nullptr, DISC_EINVAL, "diff_floor must be finite and >= 0");
-    hipError_t e = disc::launch_force(m_dev, f_dev, r_dev, rt_dev, Dims{nx, ny, nz}, diff_floor,
-                                      (hipStream_t)stream);
-    return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "force");
+    disc::GaussTaps t;
+    if (!disc::make_gauss_taps(sigma, &t)) return fail(nullptr, DISC_EINVAL, "invalid sigma");
+    const Dims d{nx, ny, nz};
+    hipError_t e = disc::launch_force_xy(m_dev, f_dev, r_dev, q_dev, rt_dev, d, diff_floor, t,
+                                         (hipStream_t)stream);
+    if (e == hipSuccess) e = disc::launch_smooth_z(q_dev, r_out_dev, d, t, (hipStream_t)stream);
+    return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "force + smoothing");
 }
 
-int disc_step_smooth(const float* rt_dev, int nx, int ny, int nz, float sigma, float* r_dev,
-                     void* stream)
+int disc_step_smooth(const float* rt_dev, int nx, int ny, int nz, float sigma, float* q_dev,
+                     float* r_dev, void* stream)
 {
-    if (!rt_dev || !r_dev) return fail(nullptr, DISC_EINVAL, "null pointer");
+    if (!rt_dev || !q_dev || !r_dev) return fail(nullptr, DISC_EINVAL, "null pointer");
     DISC_CHECK_DIMS(nx, ny, nz);
     disc::GaussTaps t;
     if (!disc::make_gauss_taps(sigma, &t)) return fail(nullptr, DISC_EINVAL, "invalid sigma");
-    hipError_t e = disc::launch_smooth(rt_dev, r_dev, Dims{nx, ny, nz}, t, (hipStream_t)stream);
+    const Dims d{nx, ny, nz};
+    hipError_t e = disc::launch_smooth_xy(rt_dev, q_dev, d, t, (hipStream_t)stream);
+    if (e == hipSuccess) e = disc::launch_smooth_z(q_dev, r_dev, d, t, (hipStream_t)stream);
     return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "smooth");
 }
 
@@ -538,14 +547,15 @@ int disc_timing_enable(disc_ctx* c, int max_records)
     return DISC_OK;
 }
 
-int disc_timing_read(disc_ctx* c, int kernel_id, int* launches, double* total_ms, double* total_voxels)
+int disc_timing_read(disc_ctx* c, int kernel_id, int level, int* launches, double* total_ms,
+                     double* total_voxels)
 {
     if (!c) return fail(nullptr, DISC_EINVAL, "context is NULL");
     if (kernel_id < 0 || kernel_id >= K_COUNT) return fail(c, DISC_EINVAL, "unknown kernel id");
     int nl = 0;
     double ms = 0.0, vox = 0.0;
     for (size_t i = 0; i < c->rec.size(); ++i) {
-        if (c->rec[i].kid != kernel_id) continue;
+        if (c->rec[i].kid != kernel_id || (level >= 0 && c->rec[i].level != level)) continue;
         hipError_t e = hipEventSynchronize(c->ev[2 * i + 1]);
         if (e != hipSuccess) return hip_fail(c, e, "event synchronize");
         float t = 0.0f;

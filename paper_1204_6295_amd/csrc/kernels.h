@@ -42,12 +42,17 @@ hipError_t launch_static_stats(const float* s, float* ys, Dims d, const int patc
 hipError_t launch_correct(const float* m, const float* ys, float* f, Dims d, const int patch[3],
                           hipStream_t st);
 
-// rt = r - u, u the Eq. 1 static-gradient force on f.
-hipError_t launch_force(const float* m, const float* f, const float* r, float* rt, Dims d,
-                        float eps_d, hipStream_t st);
+// Per z plane: r~ = r - u (u the Eq. 1 static-gradient force on f) on the tile
+// plus the Gaussian halo, then the x and y Gaussian passes: q = G_xy * r~.
+// rt (optional) receives r~.
+hipError_t launch_force_xy(const float* m, const float* f, const float* r, float* q, float* rt,
+                           Dims d, float eps_d, const GaussTaps& t, hipStream_t st);
 
-// r = G * rt per component (separable, clamped).
-hipError_t launch_smooth(const float* rt, float* r, Dims d, const GaussTaps& t, hipStream_t st);
+// q = G_xy * rt (x and y passes only).
+hipError_t launch_smooth_xy(const float* rt, float* q, Dims d, const GaussTaps& t, hipStream_t st);
+
+// out = G_z * q (z pass).
+hipError_t launch_smooth_z(const float* q, float* out, Dims d, const GaussTaps& t, hipStream_t st);
 
 // Global shift: FP64 partial sums, then s = cbct + (mean ct - mean cbct).
 size_t shift_scratch_bytes();

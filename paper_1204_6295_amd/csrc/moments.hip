@@ -1,15 +1,21 @@
 // Patch moments (Eq. 3) and the moment-matching correction (Eq. 5-6,
 // I'_s = a I_s + b) as one z-sweep kernel for gfx950.
 //
-// A 512-thread workgroup owns a 64 x 8 column tile and walks a chunk of z.
-// For each plane it stages the tile plus the in-plane patch halo in LDS,
-// forms x-window sums, then y-window sums per owned column; the z-window is
-// a ring of the last pz plane sums held in registers (pz is a template
-// parameter), so each plane is read from HBM once per tile. Sums of m and
-// m^2 are FP64: E(M^2) - E(M)^2 of 1500-HU data cancels far below FP32
-// resolution, and FP64 runs at the FP32 rate on this chip. Every window sum
-// is formed in plane/row/column order, so results do not depend on the tile
-// or chunk decomposition.
+// A workgroup owns a TS x TS column tile (TS = 32 for large volumes, 16 for
+// small ones) and walks a chunk of z. Per plane:
+//   load   the tile plus the in-plane patch halo into LDS (the next plane's
+//          global loads are issued before this plane's passes);
+//   x pass sliding window sums of m and m^2 along x, 4 outputs per item;
+//   y pass sliding window sums of those along y, 4 outputs per item;
+//   z      each thread keeps a running sum over the last pz plane sums of
+//          its column and a register ring of them (pz is a template
+//          parameter) to subtract the plane leaving the window.
+// The in-plane radius is a template parameter for isotropic-in-xy patches
+// (fully unrolled window loops) and a runtime value otherwise.
+// All window sums are FP64: E(M^2) - E(M)^2 of 1500-HU data cancels far
+// below FP32 resolution, and FP64 adds run at the FP32 rate on this chip.
+// Static and moving images go through the same code, so identical inputs
+// give bitwise identical moments.
 #include <cmath>
 
 #include "kernels.h"
@@ -18,9 +24,7 @@ namespace disc {
 
 namespace {
 
-constexpr int TX = 64;
-constexpr int TY = 8;
-constexpr int NT = TX * TY;
+constexpr int RUN = 4;
 
 struct MomArgs {
     const float* img;    // image whose patch moments are taken (m, or s at set-up)
@@ -34,114 +38,205 @@ struct MomArgs {
     double inv_n;
 };
 
-inline size_t lds_bytes(int rx, int ry)
+// Window sum over [0, 2r] of src and its squares, then RUN - 1 slides.
+template <int RC>
+__device__ inline void window_x(const float* src, int r, double2* dst)
 {
-    const size_t W = TX + 2 * rx, H = TY + 2 * ry;
-    return ((H * W * sizeof(float) + 15) & ~(size_t)15) + H * TX * sizeof(double2);
+    const int n = RC >= 0 ? 2 * RC : 2 * r;
+    double u1 = 0.0, u2 = 0.0;
+    if (RC >= 0) {
+#pragma unroll
+        for (int j = 0; j <= 2 * (RC >= 0 ? RC : 0); ++j) {
+            const double v = (double)src[j];
+            u1 += v;
+            u2 = fma(v, v, u2);
+        }
+    } else {
+#pragma unroll 4
+        for (int j = 0; j <= n; ++j) {
+            const double v = (double)src[j];
+            u1 += v;
+            u2 = fma(v, v, u2);
+        }
+    }
+    dst[0] = make_double2(u1, u2);
+#pragma unroll
+    for (int k = 1; k < RUN; ++k) {
+        const double vi = (double)src[k + n], vo = (double)src[k - 1];
+        u1 += vi - vo;
+        u2 += fma(vi, vi, -vo * vo);
+        dst[k] = make_double2(u1, u2);
+    }
 }
 
-template <int PZ, bool STATIC>
-__global__ __launch_bounds__(NT) void k_moments(MomArgs a)
+template <int PZ, int RXY, bool STATIC, int TS, int TSY>
+__global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
 {
+    constexpr int NT = TS * TSY;
+    constexpr int RMAX = RXY >= 0 ? RXY : kMaxPatchRxy;
+    constexpr int MAXH = TSY + 2 * RMAX;
+    constexpr int MAXPW = (TS + 2 * RMAX + 3) & ~3;
     constexpr int RZ = PZ / 2;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int W = TX + 2 * a.rx, H = TY + 2 * a.ry;
-    float* sm = reinterpret_cast<float*>(smem);
-    double2* sx = reinterpret_cast<double2*>(smem + (((size_t)H * W * sizeof(float) + 15) & ~(size_t)15));
+    constexpr int MAXLOAD = MAXH * MAXPW;
+    constexpr int NQ = (MAXLOAD + NT - 1) / NT;  // region values loaded per thread
+    __shared__ __align__(16) float s_m[MAXH][MAXPW];
+    __shared__ __align__(16) double2 s_x[MAXH][TS];
+    __shared__ __align__(16) double2 s_y[TSY][TS];
 
+    const int rx = RXY >= 0 ? RXY : a.rx;
+    const int ry = RXY >= 0 ? RXY : a.ry;
+    const int W = TS + 2 * rx, H = TSY + 2 * ry;
     const int lb = xcd_logical_block(blockIdx.x, a.nblocks);
     const int bx = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
     const int by = rest % a.tiles_y;
     const int bz = rest / a.tiles_y;
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * a.zchunk;
+    const int x0 = bx * TS, y0 = by * TSY, z0 = bz * a.zchunk;
     const int z1 = min(a.nz, z0 + a.zchunk);
-    const int t = threadIdx.x, lx = t % TX, ly = t / TX;
+    const int t = threadIdx.x;
+    const int lx = t % TS, ly = t / TS;
     const int ox = x0 + lx, oy = y0 + ly;
     const bool own = ox < a.nx && oy < a.ny;
     const long plane = (long)a.nx * a.ny;
 
-    double s1r[PZ], s2r[PZ];
+    double ring1[PZ], ring2[PZ];
 #pragma unroll
-    for (int k = 0; k < PZ; ++k) s1r[k] = s2r[k] = 0.0;
+    for (int k = 0; k < PZ; ++k) ring1[k] = ring2[k] = 0.0;
+    double z1s = 0.0, z2s = 0.0;
 
+    // region element i -> (row, col); precomputed once, reused every plane
+    int goff[NQ], soff[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = t + q * NT;
+        const int row = i / W, col = i - row * W;
+        if (row < H) {
+            goff[q] = clampi(y0 - ry + row, a.ny) * a.nx + clampi(x0 - rx + col, a.nx);
+            soff[q] = row * MAXPW + col;
+        } else {
+            goff[q] = -1;
+            soff[q] = 0;
+        }
+    }
+    float pre[NQ];
+    auto fetch = [&](int p) {
+        const float* src = a.img + (long)clampi(z0 - RZ + p, a.nz) * plane;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (goff[q] >= 0) pre[q] = src[goff[q]];
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (goff[q] >= 0) (&s_m[0][0])[soff[q]] = pre[q];
+    };
+
+    // the epilogue's per-voxel input (ys, or the static image itself) for the
+    // next output plane is loaded one plane ahead, off the critical path
+    const float* epi = STATIC ? a.img : a.ys_in;
+    const long col_off = (long)min(oy, a.ny - 1) * a.nx + min(ox, a.nx - 1);
+    float epi_next = 0.0f;
+
+    const int xitems = H * (TS / RUN);
     const int nplanes = (z1 - z0) + 2 * RZ;
+    fetch(0);
+    if (PZ - 1 < nplanes) epi_next = epi[(long)z0 * plane + col_off];
     for (int p0 = 0; p0 < nplanes; p0 += PZ) {
 #pragma unroll
         for (int k = 0; k < PZ; ++k) {
             const int p = p0 + k;
             if (p >= nplanes) break;
-            const float* src = a.img + (long)clampi(z0 - RZ + p, a.nz) * plane;
+            stash();
+            const float epi_cur = epi_next;
             __syncthreads();
-            for (int i = t; i < H * W; i += NT) {
-                const int row = i / W, col = i - row * W;
-                const int gx = clampi(x0 - a.rx + col, a.nx), gy = clampi(y0 - a.ry + row, a.ny);
-                sm[i] = src[(long)gy * a.nx + gx];
+            if (p + 1 < nplanes) fetch(p + 1);
+            if (p + 1 >= PZ - 1 && p + 1 < nplanes)
+                epi_next = epi[(long)(z0 + p + 1 - 2 * RZ) * plane + col_off];
+            // x pass: window [c, c + 2 rx] of the loaded row is the patch row of column c
+            for (int i = t; i < xitems; i += NT) {
+                const int run = i % (TS / RUN), row = i / (TS / RUN);
+                window_x<RXY>(&s_m[row][run * RUN], rx, &s_x[row][run * RUN]);
             }
             __syncthreads();
-            for (int i = t; i < H * TX; i += NT) {
-                const int row = i / TX, col = i - row * TX;
-                const float* q = sm + row * W + col;
+            // y pass
+            for (int i = t; i < TS * (TSY / RUN); i += NT) {
+                const int col = i % TS, run = i / TS;
                 double u1 = 0.0, u2 = 0.0;
-                for (int j = 0; j <= 2 * a.rx; ++j) {
-                    const double v = (double)q[j];
-                    u1 += v;
-                    u2 = fma(v, v, u2);
+                if (RXY >= 0) {
+#pragma unroll
+                    for (int j = 0; j <= 2 * (RXY >= 0 ? RXY : 0); ++j) {
+                        const double2 q = s_x[run * RUN + j][col];
+                        u1 += q.x;
+                        u2 += q.y;
+                    }
+                } else {
+#pragma unroll 4
+                    for (int j = 0; j <= 2 * ry; ++j) {
+                        const double2 q = s_x[run * RUN + j][col];
+                        u1 += q.x;
+                        u2 += q.y;
+                    }
                 }
-                sx[i] = make_double2(u1, u2);
+                s_y[run * RUN][col] = make_double2(u1, u2);
+#pragma unroll
+                for (int rr = 1; rr < RUN; ++rr) {
+                    const double2 qi = s_x[run * RUN + rr + 2 * ry][col], qo = s_x[run * RUN + rr - 1][col];
+                    u1 += qi.x - qo.x;
+                    u2 += qi.y - qo.y;
+                    s_y[run * RUN + rr][col] = make_double2(u1, u2);
+                }
             }
             __syncthreads();
-            double p1 = 0.0, p2 = 0.0;
-            for (int j = 0; j <= 2 * a.ry; ++j) {
-                const double2 q = sx[(ly + j) * TX + lx];
-                p1 += q.x;
-                p2 += q.y;
-            }
-            s1r[k] = p1;
-            s2r[k] = p2;
-            if (p >= PZ - 1) {
-                // planes p-PZ+1 .. p are in slots (k+1) % PZ .. k, oldest first
-                double z1s = 0.0, z2s = 0.0;
-#pragma unroll
-                for (int j = 0; j < PZ; ++j) {
-                    z1s += s1r[(k + 1 + j) % PZ];
-                    z2s += s2r[(k + 1 + j) % PZ];
-                }
+            // z: slot k holds the plane PZ planes older than p until it is replaced
+            const double2 ps = s_y[ly][lx];
+            z1s += ps.x - ring1[k];
+            z2s += ps.y - ring2[k];
+            ring1[k] = ps.x;
+            ring2[k] = ps.y;
+            if (p >= PZ - 1 && own) {
                 const int oz = z0 + p - 2 * RZ;
-                if (own) {
-                    const double mu = z1s * a.inv_n;
-                    double var = z2s * a.inv_n - mu * mu;
-                    var = var > 0.0 ? var : 0.0;
-                    const long idx = (long)oz * plane + (long)oy * a.nx + ox;
-                    if (STATIC) {
-                        // Eq. 5 denominator: STD(S). A flat static patch keeps
-                        // only the mean match and is flagged in the low bit.
-                        const double sv = (double)a.img[idx];
-                        const bool flat = !(var > (double)a.tau);
-                        const double yv = flat ? (sv - mu) : (sv - mu) / sqrt(var);
-                        unsigned b = __float_as_uint((float)yv);
-                        b = flat ? (b | 1u) : (b & ~1u);
-                        a.out[idx] = __uint_as_float(b);
-                    } else {
-                        // I'_s = a S + b = E(M) + STD(M) (S - E(S)) / STD(S), formed in
-                        // FP64 and rounded once: identical images then give
-                        // |I'_s - m| well below eps_d.
-                        const float yv = a.ys_in[idx];
-                        const double c = (__float_as_uint(yv) & 1u) ? 1.0 : sqrt(var);
-                        a.out[idx] = (float)fma(c, (double)yv, mu);
-                    }
+                const double mu = z1s * a.inv_n;
+                double var = z2s * a.inv_n - mu * mu;
+                var = var > 0.0 ? var : 0.0;
+                const long idx = (long)oz * plane + (long)oy * a.nx + ox;
+                if (STATIC) {
+                    // Eq. 5 denominator: STD(S). A flat static patch keeps only
+                    // the mean match and is flagged in the low mantissa bit.
+                    const double sv = (double)epi_cur;
+                    const bool flat = !(var > (double)a.tau);
+                    const double yv = flat ? (sv - mu) : (sv - mu) / sqrt(var);
+                    unsigned b = __float_as_uint((float)yv);
+                    b = flat ? (b | 1u) : (b & ~1u);
+                    a.out[idx] = __uint_as_float(b);
+                } else {
+                    // I'_s = a S + b = E(M) + STD(M) (S - E(S)) / STD(S), combined
+                    // in FP64 and rounded once: identical images then give
+                    // |I'_s - m| well below eps_d.
+                    const float yv = epi_cur;
+                    const double c = (__float_as_uint(yv) & 1u) ? 1.0 : (double)sqrtf((float)var);
+                    a.out[idx] = (float)fma(c, (double)yv, mu);
                 }
             }
         }
     }
 }
 
-template <bool STATIC>
-hipError_t launch_pz(int pz, dim3 g, size_t lds, hipStream_t st, const MomArgs& a)
+template <int PZ, bool STATIC, int TS>
+void launch_one(const MomArgs& a, hipStream_t st)
+{
+    const dim3 g(a.nblocks), b(TS * TS);
+    if (a.rx == PZ / 2 && a.ry == PZ / 2)
+        hipLaunchKernelGGL((k_moments<PZ, PZ / 2, STATIC, TS, TS>), g, b, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_moments<PZ, -1, STATIC, TS, TS>), g, b, 0, st, a);
+}
+
+template <bool STATIC, int TS>
+hipError_t launch_pz(int pz, hipStream_t st, const MomArgs& a)
 {
     switch (pz) {
 #define DISC_PZ(P) \
-    case P: hipLaunchKernelGGL((k_moments<P, STATIC>), g, dim3(NT), lds, st, a); break;
+    case P: launch_one<P, STATIC, TS>(a, st); break;
         DISC_PZ(1) DISC_PZ(3) DISC_PZ(5) DISC_PZ(7) DISC_PZ(9) DISC_PZ(11) DISC_PZ(13) DISC_PZ(15)
 #undef DISC_PZ
         default: return hipErrorInvalidValue;
@@ -162,19 +257,27 @@ hipError_t launch_moments(const float* img, const float* ys_in, float* out, Dims
     a.nz = d.nz;
     a.rx = patch[0] / 2;
     a.ry = patch[1] / 2;
-    a.tiles_x = (d.nx + TX - 1) / TX;
-    a.tiles_y = (d.ny + TY - 1) / TY;
-    // split z so that the launch has at least ~4 workgroups per CU
+    a.tau = tau;
+    a.inv_n = 1.0 / ((double)patch[0] * patch[1] * patch[2]);
+    // Large volumes: 32 x 32 tiles, about one 1024-thread workgroup per CU and
+    // z chunks of >= 16 planes. Small volumes: 16 x 16 tiles and short chunks,
+    // trading halo planes for parallelism.
+    const int t32 = ((d.nx + 31) / 32) * ((d.ny + 31) / 32);
+    const bool big = (long)t32 * d.nz >= 256L * 16;
+    const int TS = big ? 32 : 16;
+    a.tiles_x = (d.nx + TS - 1) / TS;
+    a.tiles_y = (d.ny + TS - 1) / TS;
     const int tiles = a.tiles_x * a.tiles_y;
-    int chunks = (1024 + tiles - 1) / tiles;
-    if (chunks > d.nz) chunks = d.nz;
+    const int target = big ? 256 : 1024;
+    const int min_chunk = big ? 16 : 2;
+    int chunks = (target + tiles - 1) / tiles;
+    const int max_chunks = (d.nz + min_chunk - 1) / min_chunk;
+    if (chunks > max_chunks) chunks = max_chunks;
     if (chunks < 1) chunks = 1;
     a.zchunk = (d.nz + chunks - 1) / chunks;
     chunks = (d.nz + a.zchunk - 1) / a.zchunk;
     a.nblocks = tiles * chunks;
-    a.tau = tau;
-    a.inv_n = 1.0 / ((double)patch[0] * patch[1] * patch[2]);
-    return launch_pz<STATIC>(patch[2], dim3(a.nblocks), lds_bytes(a.rx, a.ry), st, a);
+    return big ? launch_pz<STATIC, 32>(patch[2], st, a) : launch_pz<STATIC, 16>(patch[2], st, a);
 }
 
 }  // namespace

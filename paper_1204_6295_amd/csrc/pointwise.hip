@@ -1,11 +1,11 @@
-// Per-voxel DISC kernels for gfx950: the trilinear warp of the CT, the Eq. 1
-// force with the field update, and the set-up / level-switch kernels
-// (global shift reduction, 2x2x2 pyramid, field up-sampling).
+// Per-voxel DISC kernels for gfx950: the trilinear warp of the CT and the
+// set-up / level-switch kernels (global shift reduction, 2x2x2 pyramid,
+// field up-sampling).
 //
 // All of these are HBM-streaming kernels: one thread per voxel, x mapped to
 // the 64 lanes of a wave so every plain load and store is a contiguous
-// 256-byte wave access; gathers (warp corners, gradient neighbours) hit the
-// same or adjacent cache lines.
+// 256-byte wave access; warp-corner gathers hit the same or adjacent cache
+// lines.
 #include <cmath>
 
 #include "kernels.h"
@@ -35,17 +35,9 @@ __device__ inline int floor_to_int(float v)
 // CT sampled at x + r(x). The weights come from the fractional part of r
 // alone and the integer voxel is added separately, so FP32 keeps the full
 // sub-voxel resolution at any volume size.
-__global__ __launch_bounds__(BX * BY) void k_warp(const float* __restrict__ ct,
-                                                 const float* __restrict__ r,
-                                                 float* __restrict__ m, int nx, int ny, int nz)
+__device__ inline float warp_at(const float* __restrict__ ct, int x, int y, int z, float rx,
+                                float ry, float rz, int nx, int ny, int nz)
 {
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= nx || y >= ny) return;
-    const long N = (long)nx * ny * nz;
-    const long i = ((long)z * ny + y) * nx + x;
-    const float rx = r[i], ry = r[N + i], rz = r[2 * N + i];
     const float tx = rx - floorf(rx), ty = ry - floorf(ry), tz = rz - floorf(rz);
     const int ix = x + floor_to_int(rx), iy = y + floor_to_int(ry), iz = z + floor_to_int(rz);
     const int x0 = clampi(ix, nx), x1 = clampi(ix + 1, nx);
@@ -61,41 +53,33 @@ __global__ __launch_bounds__(BX * BY) void k_warp(const float* __restrict__ ct,
     const float c11 = fmaf(tx, p11[x1] - p11[x0], p11[x0]);
     const float c0 = fmaf(ty, c01 - c00, c00);
     const float c1 = fmaf(ty, c11 - c10, c10);
-    m[i] = fmaf(tz, c1 - c0, c0);
+    return fmaf(tz, c1 - c0, c0);
 }
 
-// Eq. 1, static-gradient term, evaluated on the corrected static image
-// f = I'_s, followed by the Algorithm A1 step-5 update. Under m(x) = CT(x + r)
-// adding the increment is r - u. Central differences with clamped neighbours.
-__global__ __launch_bounds__(BX * BY) void k_force(const float* __restrict__ m,
-                                                  const float* __restrict__ f,
-                                                  const float* __restrict__ r,
-                                                  float* __restrict__ rt, int nx, int ny, int nz,
-                                                  float eps_d)
+// Two rows per thread (y and y + BY) so that each thread has six field loads
+// and sixteen corner gathers in flight.
+__global__ __launch_bounds__(BX * BY) void k_warp(const float* __restrict__ ct,
+                                                 const float* __restrict__ r,
+                                                 float* __restrict__ m, int nx, int ny, int nz)
 {
     const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
+    const int ya = blockIdx.y * (2 * BY) + threadIdx.y, yb = ya + BY;
     const int z = blockIdx.z;
-    if (x >= nx || y >= ny) return;
-    const long plane = (long)nx * ny;
-    const long N = plane * nz;
-    const long i = (long)z * plane + (long)y * nx + x;
-    const float fc = f[i];
-    const float gx = (f[i + (x < nx - 1 ? 1 : 0)] - f[i - (x > 0 ? 1 : 0)]) * 0.5f;
-    const float gy = (f[i + (y < ny - 1 ? nx : 0)] - f[i - (y > 0 ? nx : 0)]) * 0.5f;
-    const float gz = (f[i + (z < nz - 1 ? plane : 0)] - f[i - (z > 0 ? plane : 0)]) * 0.5f;
-    const float d = m[i] - fc;
-    const float den = gx * gx + gy * gy + gz * gz + d * d;
-    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
-    if (den > 0.0f && fabsf(d) >= eps_d) {
-        const float s = d / den;
-        ux = s * gx;
-        uy = s * gy;
-        uz = s * gz;
+    if (x >= nx || ya >= ny) return;
+    const long N = (long)nx * ny * nz;
+    const long ia = ((long)z * ny + ya) * nx + x;
+    const long ib = ia + (long)BY * nx;
+    const bool has_b = yb < ny;
+    const float rxa = r[ia], rya = r[N + ia], rza = r[2 * N + ia];
+    float rxb = 0.0f, ryb = 0.0f, rzb = 0.0f;
+    if (has_b) {
+        rxb = r[ib];
+        ryb = r[N + ib];
+        rzb = r[2 * N + ib];
     }
-    rt[i] = r[i] - ux;
-    rt[N + i] = r[N + i] - uy;
-    rt[2 * N + i] = r[2 * N + i] - uz;
+    const float ma = warp_at(ct, x, ya, z, rxa, rya, rza, nx, ny, nz);
+    if (has_b) m[ib] = warp_at(ct, x, yb, z, rxb, ryb, rzb, nx, ny, nz);
+    m[ia] = ma;
 }
 
 // Sec. 2.3 multi-scale strategy: 2x2x2 block mean, clamped at odd edges.
@@ -255,15 +239,8 @@ bool make_gauss_taps(float sigma, GaussTaps* t)
 
 hipError_t launch_warp(const float* ct, const float* r, float* m, Dims d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_warp, grid_for(d), dim3(BX, BY), 0, s, ct, r, m, d.nx, d.ny, d.nz);
-    return hipGetLastError();
-}
-
-hipError_t launch_force(const float* m, const float* f, const float* r, float* rt, Dims d,
-                        float eps_d, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_force, grid_for(d), dim3(BX, BY), 0, s, m, f, r, rt, d.nx, d.ny, d.nz,
-                       eps_d);
+    const dim3 g((d.nx + BX - 1) / BX, (d.ny + 2 * BY - 1) / (2 * BY), d.nz);
+    hipLaunchKernelGGL(k_warp, g, dim3(BX, BY), 0, s, ct, r, m, d.nx, d.ny, d.nz);
     return hipGetLastError();
 }
 

@@ -1,138 +1,381 @@
-// Gaussian regularisation of the displacement field (Algorithm A1 step 6) as a
-// z-sweep kernel for gfx950.
+// Eq. 1 force, the Algorithm A1 step-5 update and the step-6 Gaussian
+// regularisation of the displacement field, as two kernels for gfx950:
 //
-// A 512-thread workgroup owns a 64 x 8 column tile of all three components
-// and walks a chunk of z. Each plane (tile plus an R-voxel halo, R =
-// ceil(3 sigma)) is staged in LDS once; the x pass and the y pass run out of
-// LDS; the z pass is a register ring of the last 2R+1 xy-filtered planes, so
-// every input plane is read from HBM once per tile and each output is
-// written once. Taps are applied in ascending offset order in every pass.
+//   k_plane_xy  one workgroup per 32 x 32 tile and chunk of z planes. It forms
+//               r~ = r - u on the tile plus the R-voxel Gaussian halo
+//               (R = ceil(3 sigma)), u being the static-gradient demons force
+//               on the corrected image f (the f plane is staged in LDS for
+//               the in-plane gradient), then runs the x and y passes out of
+//               LDS with register-blocked runs of 4 outputs and writes the
+//               xy-filtered field q. The next plane's global loads are
+//               issued before the current plane's LDS work.
+//   k_smooth_z  one thread per (x, y) column over a chunk of z: a register
+//               ring of the last 2R + 1 planes of q gives the z pass. Halo
+//               planes of a chunk are only re-read, never re-filtered.
+//
+// Splitting at the xy / z boundary keeps every filter pass free of
+// redundant halo arithmetic in z (the 13-tap passes are VALU-bound on this
+// chip) while the force is fused where its inputs are already resident.
+// Taps are applied in ascending offset order in every pass.
 #include "kernels.h"
 
 namespace disc {
 
 namespace {
 
-constexpr int TX = 64;
-constexpr int TY = 8;
-constexpr int NT = TX * TY;
+constexpr int SRUN = 4;
 
-struct SmoothArgs {
-    const float* in;
-    float* out;
+struct PlaneArgs {
+    const float* m;    // deformed moving image (force mode)
+    const float* f;    // corrected static image (force mode)
+    const float* r;    // field r (force mode) or r~ (plain smoothing)
+    float* q;          // xy-filtered r~
+    float* rt;         // optional copy of r~ (force mode), may be null
     int nx, ny, nz;
     int zchunk;
     int tiles_x, tiles_y, nblocks;
+    float eps_d;
     GaussTaps taps;
 };
 
-template <int R>
-__global__ __launch_bounds__(NT) void k_smooth(SmoothArgs a)
+template <int R, bool FORCE, int TX, int TY, bool PIPE>
+__global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
 {
+    constexpr int NT = TX * TY;
     constexpr int K = 2 * R + 1;
     constexpr int W = TX + 2 * R;
+    constexpr int PW = (W + 3) & ~3;
     constexpr int H = TY + 2 * R;
-    __shared__ float sin_[3][H][W];
-    __shared__ float sxp[3][H][TX];
+    constexpr int FW = W + 2;  // f region: one more voxel each side for the gradient
+    constexpr int FH = H + 2;
+    constexpr int XITEMS = 3 * H * (TX / SRUN);
+    constexpr int YITEMS = 3 * TX * (TY / SRUN);
+    constexpr int NF = FORCE ? (FH * FW + NT - 1) / NT : 1;  // f-region values per thread
+    constexpr int NP = (H * W + NT - 1) / NT;                // region points per thread
+    static_assert(YITEMS <= NT, "one y item per thread");
+
+    __shared__ __align__(16) float s_in[3][H][PW];
+    __shared__ __align__(16) float s_x[3][H][TX];
+    __shared__ float s_f[FORCE ? FH * FW : 1];
 
     const int lb = xcd_logical_block(blockIdx.x, a.nblocks);
     const int bx = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
     const int by = rest % a.tiles_y;
     const int bz = rest / a.tiles_y;
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * a.zchunk;
-    const int z1 = min(a.nz, z0 + a.zchunk);
-    const int t = threadIdx.x, lx = t % TX, ly = t / TX;
-    const int ox = x0 + lx, oy = y0 + ly;
-    const bool own = ox < a.nx && oy < a.ny;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int z0 = bz * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
+    const int t = threadIdx.x;
     const long plane = (long)a.nx * a.ny;
     const long N = plane * a.nz;
 
-    float ring[3][K];
+    // Per-thread geometry, fixed over the z loop. Region point q of this
+    // thread sits at clamped voxel (gx, gy); its f neighbours are the
+    // clamped voxels, looked up inside the staged f region.
+    int foff[NF], pofs[NP], pslot[NP], fc_[NP], fxp_[NP], fxm_[NP], fyp_[NP], fym_[NP];
+    bool pint[NP];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < NF; ++q) {
+        const int i = t + q * NT;
+        if (FORCE && i < FH * FW) {
+            const int row = i / FW, col = i - row * FW;
+            foff[q] = clampi(y0 - R - 1 + row, a.ny) * a.nx + clampi(x0 - R - 1 + col, a.nx);
+        } else {
+            foff[q] = -1;
+        }
+    }
 #pragma unroll
-        for (int k = 0; k < K; ++k) ring[c][k] = 0.0f;
+    for (int q = 0; q < NP; ++q) {
+        const int i = t + q * NT;
+        const int row = i / W, col = i - row * W;
+        if (i < H * W) {
+            const int gx = clampi(x0 - R + col, a.nx), gy = clampi(y0 - R + row, a.ny);
+            pofs[q] = gy * a.nx + gx;
+            pslot[q] = row * PW + col;
+            const int bxf = x0 - R - 1, byf = y0 - R - 1;
+            fc_[q] = (gy - byf) * FW + (gx - bxf);
+            fxp_[q] = (gy - byf) * FW + (clampi(gx + 1, a.nx) - bxf);
+            fxm_[q] = (gy - byf) * FW + (clampi(gx - 1, a.nx) - bxf);
+            fyp_[q] = (clampi(gy + 1, a.ny) - byf) * FW + (gx - bxf);
+            fym_[q] = (clampi(gy - 1, a.ny) - byf) * FW + (gx - bxf);
+            pint[q] = row >= R && row < R + TY && col >= R && col < R + TX && x0 - R + col < a.nx &&
+                      y0 - R + row < a.ny;
+        } else {
+            pofs[q] = -1;
+            pslot[q] = fc_[q] = fxp_[q] = fxm_[q] = fyp_[q] = fym_[q] = 0;
+            pint[q] = false;
+        }
+    }
 
+    // prefetch registers for one plane
+    float pf[NF], pr0[NP], pr1[NP], pr2[NP], pm[NP], pzu[NP], pzd[NP];
+    auto fetch = [&](int z) {
+        const long zoff = (long)z * plane;
+        if (FORCE) {
+#pragma unroll
+            for (int q = 0; q < NF; ++q)
+                if (foff[q] >= 0) pf[q] = a.f[zoff + foff[q]];
+        }
+        const long zu = (long)clampi(z + 1, a.nz) * plane, zd = (long)clampi(z - 1, a.nz) * plane;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            if (pofs[q] < 0) continue;
+            pr0[q] = a.r[zoff + pofs[q]];
+            pr1[q] = a.r[N + zoff + pofs[q]];
+            pr2[q] = a.r[2 * N + zoff + pofs[q]];
+            if (FORCE) {
+                pm[q] = a.m[zoff + pofs[q]];
+                pzu[q] = a.f[zu + pofs[q]];
+                pzd[q] = a.f[zd + pofs[q]];
+            }
+        }
+    };
+
+    if (PIPE && z0 < z1) fetch(z0);
+    for (int z = z0; z < z1; ++z) {
+        const long zoff = (long)z * plane;
+        if (!PIPE) fetch(z);
+        float v0[NP], v1[NP], v2[NP], mm[NP], fu[NP], fd[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            v0[q] = pr0[q];
+            v1[q] = pr1[q];
+            v2[q] = pr2[q];
+            mm[q] = pm[q];
+            fu[q] = pzu[q];
+            fd[q] = pzd[q];
+        }
+        if (FORCE) {
+#pragma unroll
+            for (int q = 0; q < NF; ++q)
+                if (foff[q] >= 0) s_f[t + q * NT] = pf[q];
+        }
+        __syncthreads();
+        if (PIPE && z + 1 < z1) fetch(z + 1);
+        // r~ = r - u on the tile plus halo
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            if (pofs[q] < 0) continue;
+            float w0 = v0[q], w1 = v1[q], w2 = v2[q];
+            if (FORCE) {
+                const float fcv = s_f[fc_[q]];
+                const float gxv = (s_f[fxp_[q]] - s_f[fxm_[q]]) * 0.5f;
+                const float gyv = (s_f[fyp_[q]] - s_f[fym_[q]]) * 0.5f;
+                const float gzv = (fu[q] - fd[q]) * 0.5f;
+                const float d = mm[q] - fcv;
+                const float den = gxv * gxv + gyv * gyv + gzv * gzv + d * d;
+                if (den > 0.0f && fabsf(d) >= a.eps_d) {
+                    const float sc = d / den;
+                    w0 -= sc * gxv;
+                    w1 -= sc * gyv;
+                    w2 -= sc * gzv;
+                }
+                if (a.rt && pint[q]) {
+                    a.rt[zoff + pofs[q]] = w0;
+                    a.rt[N + zoff + pofs[q]] = w1;
+                    a.rt[2 * N + zoff + pofs[q]] = w2;
+                }
+            }
+            (&s_in[0][0][0])[pslot[q]] = w0;
+            (&s_in[1][0][0])[pslot[q]] = w1;
+            (&s_in[2][0][0])[pslot[q]] = w2;
+        }
+        __syncthreads();
+        // x pass: 4 consecutive outputs of one row per item
+        for (int i = t; i < XITEMS; i += NT) {
+            const int run = i % (TX / SRUN), cr = i / (TX / SRUN);
+            const int c = cr / H, row = cr - c * H;
+            const float* src = &s_in[c][row][run * SRUN];
+            float v[(SRUN + 2 * R + 3) & ~3];
+#pragma unroll
+            for (int j = 0; j < (SRUN + 2 * R + 3) / 4; ++j) {
+                const float4 w4 = *reinterpret_cast<const float4*>(src + 4 * j);
+                v[4 * j] = w4.x;
+                v[4 * j + 1] = w4.y;
+                v[4 * j + 2] = w4.z;
+                v[4 * j + 3] = w4.w;
+            }
+            float o[SRUN];
+#pragma unroll
+            for (int rr = 0; rr < SRUN; ++rr) {
+                float sacc = 0.0f;
+#pragma unroll
+                for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[rr + j], sacc);
+                o[rr] = sacc;
+            }
+            *reinterpret_cast<float4*>(&s_x[c][row][run * SRUN]) = make_float4(o[0], o[1], o[2], o[3]);
+        }
+        __syncthreads();
+        // y pass: 4 consecutive outputs of one column per item, written to q
+        if (t < YITEMS) {
+            const int col = t % TX, cr = t / TX;
+            const int run = cr % (TY / SRUN), c = cr / (TY / SRUN);
+            float v[SRUN + 2 * R];
+#pragma unroll
+            for (int j = 0; j < SRUN + 2 * R; ++j) v[j] = s_x[c][run * SRUN + j][col];
+            const int ox = x0 + col;
+#pragma unroll
+            for (int rr = 0; rr < SRUN; ++rr) {
+                float sacc = 0.0f;
+#pragma unroll
+                for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[rr + j], sacc);
+                const int oy = y0 + run * SRUN + rr;
+                if (ox < a.nx && oy < a.ny) a.q[c * N + zoff + (long)oy * a.nx + ox] = sacc;
+            }
+        }
+    }
+}
+
+struct ZArgs {
+    const float* q;
+    float* out;
+    int nx, ny, nz;
+    int zchunk;
+    long ncols;
+    GaussTaps taps;
+};
+
+constexpr int ZNT = 256;
+
+template <int R>
+__global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
+{
+    constexpr int K = 2 * R + 1;
+    const long col = (long)blockIdx.x * ZNT + threadIdx.x;
+    if (col >= a.ncols) return;
+    const int z0 = blockIdx.y * a.zchunk;
+    const int z1 = min(a.nz, z0 + a.zchunk);
+    const long plane = (long)a.nx * a.ny;
+    const long N = plane * a.nz;
+    float ring[3][K];
+    float n1[3], n2[3];  // the next two planes, loads in flight
+    auto load = [&](int p, float* dst) {
+        const long o = (long)clampi(z0 - R + p, a.nz) * plane + col;
+        dst[0] = a.q[o];
+        dst[1] = a.q[N + o];
+        dst[2] = a.q[2 * N + o];
+    };
     const int nplanes = (z1 - z0) + 2 * R;
+    load(0, n1);
+    if (nplanes > 1) load(1, n2);
     for (int p0 = 0; p0 < nplanes; p0 += K) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int p = p0 + k;
             if (p >= nplanes) break;
-            const long zoff = (long)clampi(z0 - R + p, a.nz) * plane;
-            __syncthreads();
-            for (int i = t; i < 3 * H * W; i += NT) {
-                const int c = i / (H * W);
-                const int rem = i - c * (H * W);
-                const int row = rem / W, col = rem - row * W;
-                const int gx = clampi(x0 - R + col, a.nx), gy = clampi(y0 - R + row, a.ny);
-                sin_[c][row][col] = a.in[c * N + zoff + (long)gy * a.nx + gx];
-            }
-            __syncthreads();
-            for (int i = t; i < 3 * H * TX; i += NT) {
-                const int c = i / (H * TX);
-                const int rem = i - c * (H * TX);
-                const int row = rem / TX, col = rem - row * TX;
-                float s = 0.0f;
-#pragma unroll
-                for (int j = 0; j < K; ++j) s = fmaf(a.taps.w[j], sin_[c][row][col + j], s);
-                sxp[c][row][col] = s;
-            }
-            __syncthreads();
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                float s = 0.0f;
-#pragma unroll
-                for (int j = 0; j < K; ++j) s = fmaf(a.taps.w[j], sxp[c][ly + j][lx], s);
-                ring[c][k] = s;
+                ring[c][k] = n1[c];
+                n1[c] = n2[c];
             }
+            if (p + 2 < nplanes) load(p + 2, n2);
             if (p >= K - 1) {
-                const int oz = z0 + p - 2 * R;
-                if (own) {
-                    const long idx = (long)oz * plane + (long)oy * a.nx + ox;
+                const long o = (long)(z0 + p - 2 * R) * plane + col;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        float s = 0.0f;
+                for (int c = 0; c < 3; ++c) {
+                    float sacc = 0.0f;
 #pragma unroll
-                        for (int j = 0; j < K; ++j) s = fmaf(a.taps.w[j], ring[c][(k + 1 + j) % K], s);
-                        a.out[c * N + idx] = s;
-                    }
+                    for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], ring[c][(k + 1 + j) % K], sacc);
+                    a.out[c * N + o] = sacc;
                 }
             }
         }
     }
 }
 
-}  // namespace
+// Tile of the xy kernel: 32 x 32 columns, 1024 threads, next plane prefetched.
+constexpr int PTX = 32;
+constexpr int PTY = 32;
+constexpr bool PPIPE = true;
 
-hipError_t launch_smooth(const float* rt, float* r, Dims d, const GaussTaps& t, hipStream_t st)
+template <bool FORCE>
+hipError_t launch_plane(const PlaneArgs& a, int R, hipStream_t st)
 {
-    SmoothArgs a;
-    a.in = rt;
-    a.out = r;
+    const dim3 g(a.nblocks);
+    switch (R) {
+#define DISC_R(RR) \
+    case RR: hipLaunchKernelGGL((k_plane_xy<RR, FORCE, PTX, PTY, PPIPE>), g, dim3(PTX * PTY), 0, st, a); break;
+        DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
+#undef DISC_R
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_z(const float* q, float* out, Dims d, const GaussTaps& t, hipStream_t st)
+{
+    ZArgs a;
+    a.q = q;
+    a.out = out;
     a.nx = d.nx;
     a.ny = d.ny;
     a.nz = d.nz;
-    a.tiles_x = (d.nx + TX - 1) / TX;
-    a.tiles_y = (d.ny + TY - 1) / TY;
+    a.ncols = (long)d.nx * d.ny;
+    a.taps = t;
+    // z chunks: about 4 workgroups per CU; re-read halo planes come from cache
+    const long colblocks = (a.ncols + ZNT - 1) / ZNT;
+    int chunks = (int)((2048 + colblocks - 1) / colblocks);
+    if (chunks > d.nz) chunks = d.nz;
+    if (chunks < 1) chunks = 1;
+    a.zchunk = (d.nz + chunks - 1) / chunks;
+    chunks = (d.nz + a.zchunk - 1) / a.zchunk;
+    const dim3 g((unsigned)colblocks, (unsigned)chunks);
+    switch (t.R) {
+#define DISC_R(RR) \
+    case RR: hipLaunchKernelGGL(k_smooth_z<RR>, g, dim3(ZNT), 0, st, a); break;
+        DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
+#undef DISC_R
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+PlaneArgs plane_args(Dims d, const GaussTaps& t, int tx = PTX, int ty = PTY, int target = 512)
+{
+    PlaneArgs a{};
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.tiles_x = (d.nx + tx - 1) / tx;
+    a.tiles_y = (d.ny + ty - 1) / ty;
+    // z chunks: about `target` workgroups in the launch
     const int tiles = a.tiles_x * a.tiles_y;
-    int chunks = (1024 + tiles - 1) / tiles;
+    int chunks = (target + tiles - 1) / tiles;
     if (chunks > d.nz) chunks = d.nz;
     if (chunks < 1) chunks = 1;
     a.zchunk = (d.nz + chunks - 1) / chunks;
     chunks = (d.nz + a.zchunk - 1) / a.zchunk;
     a.nblocks = tiles * chunks;
     a.taps = t;
-    const dim3 g(a.nblocks);
-    switch (t.R) {
-#define DISC_R(RR) \
-    case RR: hipLaunchKernelGGL(k_smooth<RR>, g, dim3(NT), 0, st, a); break;
-        DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
-#undef DISC_R
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return a;
+}
+
+}  // namespace
+
+hipError_t launch_force_xy(const float* m, const float* f, const float* r, float* q, float* rt,
+                           Dims d, float eps_d, const GaussTaps& t, hipStream_t st)
+{
+    PlaneArgs a = plane_args(d, t);
+    a.m = m;
+    a.f = f;
+    a.r = r;
+    a.q = q;
+    a.rt = rt;
+    a.eps_d = eps_d;
+    return launch_plane<true>(a, t.R, st);
+}
+
+hipError_t launch_smooth_xy(const float* rt, float* q, Dims d, const GaussTaps& t, hipStream_t st)
+{
+    PlaneArgs a = plane_args(d, t);
+    a.r = rt;
+    a.q = q;
+    return launch_plane<false>(a, t.R, st);
+}
+
+hipError_t launch_smooth_z(const float* q, float* out, Dims d, const GaussTaps& t, hipStream_t st)
+{
+    return launch_z(q, out, d, t, st);
 }
 
 }  // namespace disc

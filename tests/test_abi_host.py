@@ -113,7 +113,7 @@ def test_state_errors_without_gpu(disc):
         assert L.disc_set_volumes(h, fake, fake, 64, 64, 64, fake, 1000, None) == disc.DISC_ENOMEM
         assert b"needs" in L.disc_last_error(h)
         assert L.disc_iterate(h, -1, None) == disc.DISC_ESTATE
-        assert L.disc_timing_read(h, 9, None, None, None) == disc.DISC_EINVAL
+        assert L.disc_timing_read(h, 9, -1, None, None, None) == disc.DISC_EINVAL
         assert L.disc_timing_enable(h, -1) == disc.DISC_EINVAL
     finally:
         L.disc_destroy(h)
@@ -129,8 +129,11 @@ def test_step_argument_errors_without_gpu(disc):
     assert L.disc_step_warp(fake, fake, 4, 4, 70000, fake, None) == disc.DISC_EINVAL
     assert L.disc_step_correct(fake, fake, 4, 4, 4, bad, fake, None) == disc.DISC_EINVAL
     assert L.disc_step_static_stats(fake, 4, 4, 4, patch, -1.0, fake, None) == disc.DISC_EINVAL
-    assert L.disc_step_force(fake, fake, fake, 4, 4, 4, float("inf"), fake, None) == disc.DISC_EINVAL
-    assert L.disc_step_smooth(fake, 4, 4, 4, 3.0, fake, None) == disc.DISC_EINVAL
+    assert L.disc_step_force_smooth(fake, fake, fake, 4, 4, 4, 2.0, float("inf"), fake, fake, None,
+                                    None) == disc.DISC_EINVAL
+    assert L.disc_step_force_smooth(fake, fake, fake, 4, 4, 4, 2.0, 1e-3, None, fake, None,
+                                    None) == disc.DISC_EINVAL
+    assert L.disc_step_smooth(fake, 4, 4, 4, 3.0, fake, fake, None) == disc.DISC_EINVAL
     assert L.disc_step_shift(fake, fake, 0, fake, None, fake, 1 << 20, None) == disc.DISC_EINVAL
     assert L.disc_step_shift(fake, fake, 10, fake, None, fake, 8, None) == disc.DISC_ENOMEM
     assert L.disc_step_upsample_field(fake, 0, 1, 1, fake, 2, 2, 2, None) == disc.DISC_EINVAL

@@ -2,8 +2,9 @@
 
 Every step runs through the C ABI (disc_step_*), i.e. the same kernels as
 disc_iterate, on identical FP32 inputs; the oracle promotes them to FP64.
-Shapes span several 64 x 8 tiles with ragged tails in x, y and z, plus
-degenerate volumes (single voxel, single row, dims below the patch size).
+Shapes span several 32 x 32 (and 16 x 16) tiles with ragged tails in x, y
+and z, plus degenerate volumes (single voxel, single row, dims below the
+patch size).
 Bar: max|gpu - ref| / max|ref| <= 1e-4 per output array.
 """
 import numpy as np
@@ -84,20 +85,27 @@ def test_correct_on_phantom_with_flat_regions(disc):
         assert (var_s <= 1e-2).sum() > 0
 
 
-@pytest.mark.parametrize("shape", SHAPES)
-def test_force(disc, shape):
+@pytest.mark.parametrize("shape", SHAPES + [(40, 70, 66)])
+@pytest.mark.parametrize("sigma", [1.5, 2.0])
+def test_force_and_smooth(disc, shape, sigma):
+    """Production force + Gaussian kernels: r - u against the oracle's Eq. 1
+    force, and the smoothed field against the oracle Gaussian of the GPU's
+    own r - u (identical FP32 input)."""
     g = rng(4)
     m = (g.normal(size=shape) * 300).astype(np.float32)
     f = (m + g.normal(size=shape) * 40).astype(np.float32)
     f.flat[:: 7] = m.flat[:: 7]  # d = 0 exactly: zero force
     r = g.uniform(-2, 2, size=(3,) + shape).astype(np.float32)
-    rt = to_np(disc.force(to_dev(m), to_dev(f), to_dev(r), 1e-3))
+    out, rt = disc.force_smooth(to_dev(m), to_dev(f), to_dev(r), sigma, 1e-3, want_rt=True)
+    out, rt = to_np(out), to_np(rt)
     u_ref = oracle.force(m, f, 1e-3)
     ref = r.astype(np.float64) - u_ref
     assert rel_err(rt, ref) <= STEP_RTOL
     u_gpu = r.astype(np.float64) - rt.astype(np.float64)
     assert np.abs(u_gpu - u_ref).max() <= 1e-5
     assert np.sqrt((u_gpu ** 2).sum(0)).max() <= 0.5 + 1e-6
+    sref = np.stack([oracle.gauss(rt[c], sigma) for c in range(3)])
+    assert rel_err(out, sref) <= STEP_RTOL
 
 
 @pytest.mark.parametrize("sigma", [0.3, 0.7, 1.5, 2.0, 2.6])
