@@ -106,29 +106,27 @@ __global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
 
     // region element i -> (row, col); precomputed once, reused every plane
     int goff[NQ], soff[NQ];
+    bool gval[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int i = t + q * NT;
         const int row = i / W, col = i - row * W;
-        if (row < H) {
-            goff[q] = clampi(y0 - ry + row, a.ny) * a.nx + clampi(x0 - rx + col, a.nx);
-            soff[q] = row * MAXPW + col;
-        } else {
-            goff[q] = -1;
-            soff[q] = 0;
-        }
+        gval[q] = row < H;
+        // out-of-region slots load a valid address and are never stored, so
+        // the loads stay branch-free and remain in flight across barriers
+        goff[q] = gval[q] ? clampi(y0 - ry + row, a.ny) * a.nx + clampi(x0 - rx + col, a.nx) : 0;
+        soff[q] = gval[q] ? row * MAXPW + col : 0;
     }
     float pre[NQ];
     auto fetch = [&](int p) {
         const float* src = a.img + (long)clampi(z0 - RZ + p, a.nz) * plane;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            if (goff[q] >= 0) pre[q] = src[goff[q]];
+        for (int q = 0; q < NQ; ++q) pre[q] = src[goff[q]];
     };
     auto stash = [&]() {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            if (goff[q] >= 0) (&s_m[0][0])[soff[q]] = pre[q];
+            if (gval[q]) (&s_m[0][0])[soff[q]] = pre[q];
     };
 
     // the epilogue's per-voxel input (ys, or the static image itself) for the
@@ -140,7 +138,7 @@ __global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
     const int xitems = H * (TS / RUN);
     const int nplanes = (z1 - z0) + 2 * RZ;
     fetch(0);
-    if (PZ - 1 < nplanes) epi_next = epi[(long)z0 * plane + col_off];
+    epi_next = epi[(long)z0 * plane + col_off];
     for (int p0 = 0; p0 < nplanes; p0 += PZ) {
 #pragma unroll
         for (int k = 0; k < PZ; ++k) {
@@ -149,9 +147,8 @@ __global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
             stash();
             const float epi_cur = epi_next;
             __syncthreads();
-            if (p + 1 < nplanes) fetch(p + 1);
-            if (p + 1 >= PZ - 1 && p + 1 < nplanes)
-                epi_next = epi[(long)(z0 + p + 1 - 2 * RZ) * plane + col_off];
+            fetch(p + 1);  // past the chunk end this re-reads a clamped plane
+            epi_next = epi[(long)clampi(z0 + p + 1 - 2 * RZ, a.nz) * plane + col_off];
             // x pass: window [c, c + 2 rx] of the loaded row is the patch row of column c
             for (int i = t; i < xitems; i += NT) {
                 const int run = i % (TS / RUN), row = i / (TS / RUN);

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
     // thread sits at clamped voxel (gx, gy); its f neighbours are the
     // clamped voxels, looked up inside the staged f region.
     int foff[NF], pofs[NP], pslot[NP], fc_[NP], fxp_[NP], fxm_[NP], fyp_[NP], fym_[NP];
-    bool pint[NP];
+    bool fval[NF], pval[NP], pint[NP];
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
         const int i = t + q * NT;
@@ -81,8 +81,9 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
             const int row = i / FW, col = i - row * FW;
             foff[q] = clampi(y0 - R - 1 + row, a.ny) * a.nx + clampi(x0 - R - 1 + col, a.nx);
         } else {
-            foff[q] = -1;
+            foff[q] = 0;  // loaded but never stored: keeps the load branch-free
         }
+        fval[q] = FORCE && i < FH * FW;
     }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
@@ -100,26 +101,28 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
             fym_[q] = (clampi(gy - 1, a.ny) - byf) * FW + (gx - bxf);
             pint[q] = row >= R && row < R + TY && col >= R && col < R + TX && x0 - R + col < a.nx &&
                       y0 - R + row < a.ny;
+            pval[q] = true;
         } else {
-            pofs[q] = -1;
-            pslot[q] = fc_[q] = fxp_[q] = fxm_[q] = fyp_[q] = fym_[q] = 0;
+            // loaded but never used: keeps the loads branch-free
+            pofs[q] = pslot[q] = fc_[q] = fxp_[q] = fxm_[q] = fyp_[q] = fym_[q] = 0;
             pint[q] = false;
+            pval[q] = false;
         }
     }
 
-    // prefetch registers for one plane
+    // prefetch registers for one plane; every load is unconditional (no
+    // divergent branches), so the compiler can keep them in flight across
+    // the barriers of the current plane
     float pf[NF], pr0[NP], pr1[NP], pr2[NP], pm[NP], pzu[NP], pzd[NP];
     auto fetch = [&](int z) {
         const long zoff = (long)z * plane;
         if (FORCE) {
 #pragma unroll
-            for (int q = 0; q < NF; ++q)
-                if (foff[q] >= 0) pf[q] = a.f[zoff + foff[q]];
+            for (int q = 0; q < NF; ++q) pf[q] = a.f[zoff + foff[q]];
         }
         const long zu = (long)clampi(z + 1, a.nz) * plane, zd = (long)clampi(z - 1, a.nz) * plane;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            if (pofs[q] < 0) continue;
             pr0[q] = a.r[zoff + pofs[q]];
             pr1[q] = a.r[N + zoff + pofs[q]];
             pr2[q] = a.r[2 * N + zoff + pofs[q]];
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
         }
     };
 
-    if (PIPE && z0 < z1) fetch(z0);
+    if (PIPE) fetch(z0 < z1 ? z0 : 0);
     for (int z = z0; z < z1; ++z) {
         const long zoff = (long)z * plane;
         if (!PIPE) fetch(z);
@@ -148,14 +151,14 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
         if (FORCE) {
 #pragma unroll
             for (int q = 0; q < NF; ++q)
-                if (foff[q] >= 0) s_f[t + q * NT] = pf[q];
+                if (fval[q]) s_f[t + q * NT] = pf[q];
         }
         __syncthreads();
-        if (PIPE && z + 1 < z1) fetch(z + 1);
+        if (PIPE) fetch(min(z + 1, z1 - 1));
         // r~ = r - u on the tile plus halo
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            if (pofs[q] < 0) continue;
+            if (!pval[q]) continue;
             float w0 = v0[q], w1 = v1[q], w2 = v2[q];
             if (FORCE) {
                 const float fcv = s_f[fc_[q]];
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
     };
     const int nplanes = (z1 - z0) + 2 * R;
     load(0, n1);
-    if (nplanes > 1) load(1, n2);
+    load(1, n2);  // clamped plane index: always a valid address
     for (int p0 = 0; p0 < nplanes; p0 += K) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
                 ring[c][k] = n1[c];
                 n1[c] = n2[c];
             }
-            if (p + 2 < nplanes) load(p + 2, n2);
+            load(p + 2, n2);  // past the chunk end this re-reads a clamped plane
             if (p >= K - 1) {
                 const long o = (long)(z0 + p - 2 * R) * plane + col;
 #pragma unroll
