@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--workload", default="hn256x256x96", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events in the timed steps")
+    ap.add_argument("--dump-inputs", metavar="DIR",
+                    help="write the workload's CT and CBCT as raw float32 files (for the native driver) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs DISC on a single MI355X "
@@ -105,6 +107,12 @@ def main():
     cfg = CONFIGS[cname]
     log("generating %s phantom pair %s" % (args.workload, cfg["shape"]))
     case = make_case(cname, device="cuda")
+    if args.dump_inputs:
+        os.makedirs(args.dump_inputs, exist_ok=True)
+        case.ct.tofile(os.path.join(args.dump_inputs, "ct.f32"))
+        case.cbct.tofile(os.path.join(args.dump_inputs, "cbct.f32"))
+        log("wrote %s/{ct,cbct}.f32, shape (nz, ny, nx) = %s" % (args.dump_inputs, cfg["shape"]))
+        return
     ct = torch.from_numpy(case.ct).to(dev)
     cb = torch.from_numpy(case.cbct).to(dev)
     params = dict(patch=cfg["patch"], sigma=cfg["sigma"], levels=cfg["levels"], iters=cfg["iters"])
@@ -119,9 +127,7 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
-    launches_per_step = 4 * sum(cfg["iters"]) + (cfg["levels"] - 1)
-    if not args.no_timing:
-        reg.timing_enable(launches_per_step * args.steps + 16)
+    # timed steps: no instrumentation, the value is the plain throughput
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -130,6 +136,15 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1000.0 / args.steps
     log("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step))
+
+    # the same steps again with a HIP event pair around every kernel launch,
+    # recorded on the launch stream: per-kernel averages for the roofline
+    launches_per_step = 4 * sum(cfg["iters"]) + (cfg["levels"] - 1)
+    if not args.no_timing:
+        reg.timing_enable(launches_per_step * args.steps + 16)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
 
     # voxel-iterations per step over all levels
     dims = [tuple(cfg["shape"])]

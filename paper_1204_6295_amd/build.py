@@ -13,6 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libdisc.so")
+BENCH_EXE = os.path.join(HERE, "disc_bench")
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -26,6 +27,18 @@ FLAGS = [
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+def _link_driver():
+    """Native driver of the C ABI (disc_bench), linked against libdisc.so."""
+    src = os.path.join(CSRC, "disc_bench_main.cpp")
+    tmp = BENCH_EXE + ".tmp"
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I" + INCLUDE, src, "-o", tmp, "-L" + HERE, "-ldisc",
+           "-Wl,-rpath,$ORIGIN"]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("driver build failed:\n" + p.stdout + p.stderr)
+    os.replace(tmp, BENCH_EXE)
 
 
 def _compile(src):
@@ -56,6 +69,7 @@ def build(verbose=False):
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stdout + p.stderr)
     os.replace(tmp, OUT)
+    _link_driver()
     return OUT
 
 

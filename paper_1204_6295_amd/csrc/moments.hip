@@ -5,7 +5,9 @@
 // small ones) and walks a chunk of z. Per plane:
 //   load   the tile plus the in-plane patch halo into LDS (the next plane's
 //          global loads are issued before this plane's passes);
-//   x pass sliding window sums of m and m^2 along x, 4 outputs per item;
+//   x pass sliding window sums of m and m^2 along x, 4 outputs per item,
+//          one lane per row, stored column-major with an odd pitch so the
+//          writes here and the reads of the y pass are bank-conflict free;
 //   y pass sliding window sums of those along y, 4 outputs per item;
 //   z      each thread keeps a running sum over the last pz plane sums of
 //          its column and a register ring of them (pz is a template
@@ -38,9 +40,10 @@ struct MomArgs {
     double inv_n;
 };
 
-// Window sum over [0, 2r] of src and its squares, then RUN - 1 slides.
+// Window sum over [0, 2r] of src and its squares, then RUN - 1 slides; the
+// RUN results go to dst[0], dst[stride], ...
 template <int RC>
-__device__ inline void window_x(const float* src, int r, double2* dst)
+__device__ inline void window_x(const float* src, int r, double2* dst, int stride)
 {
     const int n = RC >= 0 ? 2 * RC : 2 * r;
     double u1 = 0.0, u2 = 0.0;
@@ -65,7 +68,7 @@ __device__ inline void window_x(const float* src, int r, double2* dst)
         const double vi = (double)src[k + n], vo = (double)src[k - 1];
         u1 += vi - vo;
         u2 += fma(vi, vi, -vo * vo);
-        dst[k] = make_double2(u1, u2);
+        dst[k * stride] = make_double2(u1, u2);
     }
 }
 
@@ -79,8 +82,10 @@ __global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
     constexpr int RZ = PZ / 2;
     constexpr int MAXLOAD = MAXH * MAXPW;
     constexpr int NQ = (MAXLOAD + NT - 1) / NT;  // region values loaded per thread
+    constexpr int PXH = MAXH | 1;  // odd pitch: column-major x sums are bank-conflict free
+    static_assert(MAXH <= 64, "one lane per loaded row in the x pass");
     __shared__ __align__(16) float s_m[MAXH][MAXPW];
-    __shared__ __align__(16) double2 s_x[MAXH][TS];
+    __shared__ __align__(16) double2 s_x[TS][PXH];  // x sums, column-major
     __shared__ __align__(16) double2 s_y[TSY][TS];
 
     const int rx = RXY >= 0 ? RXY : a.rx;
@@ -135,7 +140,6 @@ __global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
     const long col_off = (long)min(oy, a.ny - 1) * a.nx + min(ox, a.nx - 1);
     float epi_next = 0.0f;
 
-    const int xitems = H * (TS / RUN);
     const int nplanes = (z1 - z0) + 2 * RZ;
     fetch(0);
     epi_next = epi[(long)z0 * plane + col_off];
@@ -149,10 +153,11 @@ __global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
             __syncthreads();
             fetch(p + 1);  // past the chunk end this re-reads a clamped plane
             epi_next = epi[(long)clampi(z0 + p + 1 - 2 * RZ, a.nz) * plane + col_off];
-            // x pass: window [c, c + 2 rx] of the loaded row is the patch row of column c
-            for (int i = t; i < xitems; i += NT) {
-                const int run = i % (TS / RUN), row = i / (TS / RUN);
-                window_x<RXY>(&s_m[row][run * RUN], rx, &s_x[row][run * RUN]);
+            // x pass: window [c, c + 2 rx] of the loaded row is the patch row of
+            // column c. One lane per row, one wave per run of 4 columns.
+            for (int i = t; i < 64 * (TS / RUN); i += NT) {
+                const int row = i & 63, run = i >> 6;
+                if (row < H) window_x<RXY>(&s_m[row][run * RUN], rx, &s_x[run * RUN][row], PXH);
             }
             __syncthreads();
             // y pass
@@ -162,14 +167,14 @@ __global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
                 if (RXY >= 0) {
 #pragma unroll
                     for (int j = 0; j <= 2 * (RXY >= 0 ? RXY : 0); ++j) {
-                        const double2 q = s_x[run * RUN + j][col];
+                        const double2 q = s_x[col][run * RUN + j];
                         u1 += q.x;
                         u2 += q.y;
                     }
                 } else {
 #pragma unroll 4
                     for (int j = 0; j <= 2 * ry; ++j) {
-                        const double2 q = s_x[run * RUN + j][col];
+                        const double2 q = s_x[col][run * RUN + j];
                         u1 += q.x;
                         u2 += q.y;
                     }
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(TS* TSY) void k_moments(MomArgs a)
                 s_y[run * RUN][col] = make_double2(u1, u2);
 #pragma unroll
                 for (int rr = 1; rr < RUN; ++rr) {
-                    const double2 qi = s_x[run * RUN + rr + 2 * ry][col], qo = s_x[run * RUN + rr - 1][col];
+                    const double2 qi = s_x[col][run * RUN + rr + 2 * ry], qo = s_x[col][run * RUN + rr - 1];
                     u1 += qi.x - qo.x;
                     u2 += qi.y - qo.y;
                     s_y[run * RUN + rr][col] = make_double2(u1, u2);

@@ -168,7 +168,9 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
                 const float d = mm[q] - fcv;
                 const float den = gxv * gxv + gyv * gyv + gzv * gzv + d * d;
                 if (den > 0.0f && fabsf(d) >= a.eps_d) {
-                    const float sc = d / den;
+                    // den >= d^2 >= eps_d^2 is a normal number: the hardware
+                    // reciprocal (1 ulp) replaces the IEEE division sequence
+                    const float sc = d * __builtin_amdgcn_rcpf(den);
                     w0 -= sc * gxv;
                     w1 -= sc * gyv;
                     w2 -= sc * gzv;
