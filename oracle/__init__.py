@@ -95,6 +95,11 @@ def lib():
         L.orc_correct_pts.argtypes = [_F, _F, _I, _I, _I, _I, _I, _I, ctypes.c_double, _L, ctypes.c_long, _D]
         L.orc_force_pts.argtypes = [_F, _F, _F, _I, _I, _I, ctypes.c_double, _L, ctypes.c_long, _D]
         L.orc_gauss_pts.argtypes = [_F, _I, _I, _I, ctypes.c_double, _L, ctypes.c_long, _D]
+        L.orc_ssd_loss.restype = ctypes.c_double
+        L.orc_ssd_loss.argtypes = [_D, _D, _D, _I, _I, _I, _I, _I, _I, ctypes.c_double]
+        L.orc_ssd_grad.argtypes = [_D, _D, _D, _I, _I, _I, _I, _I, _I, ctypes.c_double, _D]
+        L.orc_ssd_grad_pts.argtypes = [_F, _F, _F, _I, _I, _I, _I, _I, _I, ctypes.c_double, _L,
+                                       ctypes.c_long, _D]
         _lib = L
     return _lib
 
@@ -281,4 +286,39 @@ def gauss_pts(rt, sigma, pts):
     nx, ny, nz = _dims(rt)
     out = np.empty((pts.size, 3))
     lib().orc_gauss_pts(pr, nx, ny, nz, float(sigma), pp, pts.size, out.ctypes.data_as(_D))
+    return out
+
+
+def ssd_loss(ct, s, r, patch, tau=1e-2):
+    """L = sum (m - I'_s)^2 with m = warp(ct, r) (FP64)."""
+    ct, pc = _d(ct)
+    s, ps = _d(s)
+    r, pr = _d(r)
+    nx, ny, nz = _dims(ct)
+    return lib().orc_ssd_loss(pc, ps, pr, nx, ny, nz, int(patch[0]), int(patch[1]), int(patch[2]),
+                              float(tau))
+
+
+def ssd_grad(ct, s, r, patch, tau=1e-2):
+    """Analytic dL/dr, shape (3, nz, ny, nx)."""
+    ct, pc = _d(ct)
+    s, ps = _d(s)
+    r, pr = _d(r)
+    nx, ny, nz = _dims(ct)
+    out = np.empty((3,) + ct.shape)
+    lib().orc_ssd_grad(pc, ps, pr, nx, ny, nz, int(patch[0]), int(patch[1]), int(patch[2]),
+                       float(tau), out.ctypes.data_as(_D))
+    return out
+
+
+def ssd_grad_pts(ct, s, r, patch, pts, tau=1e-2):
+    """dL/dr at linear voxel indices pts from FP32 state; returns (npts, 3)."""
+    ct, pc = _f(ct)
+    s, ps = _f(s)
+    r, pr = _f(r)
+    nx, ny, nz = _dims(ct)
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    out = np.empty((len(pts), 3))
+    lib().orc_ssd_grad_pts(pc, ps, pr, nx, ny, nz, int(patch[0]), int(patch[1]), int(patch[2]),
+                           float(tau), pts.ctypes.data_as(_L), len(pts), out.ctypes.data_as(_D))
     return out

@@ -510,3 +510,195 @@ void orc_gauss_pts(const float* rt, int nx, int ny, int nz, double sigma,
         }
     }
 }
+
+/* ---- differentiable DISC: SSD between m and I'_s --------------------------
+ *
+ * Loss L(r) = sum_x (m(x) - I'_s(x))^2 with m = warp(CT, r) (Sec. 2.1 model)
+ * and I'_s = a S + b from the patch moments of m and S (Eq. 3-6). The
+ * gradient is the chain rule written out:
+ *   dL/dm_j = 2 D_j - 2 sum_x D_x dI'_s(x)/dm_j,   D = m - I'_s,
+ *   dI'_s(x)/dm_j = sum over patch offsets k with clamp(x + k) = j of
+ *                   1/n + Y_x (m_j - E_x(M)) / (n STD_x(M)),
+ * where Y = (S - E(S)) / STD(S); a flat static patch (a := 1) contributes
+ * 1/n only, and so does a patch with STD(M) = 0 (a is not differentiable
+ * there; its one-sided choice is 0). dL/dr = dL/dm * d trilinear / d position.
+ */
+
+/* Derivative of the trilinear interpolant of trilinear() with respect to the
+ * sample position, same floor and clamp conventions. */
+static void trilinear_grad(const double* v, int nx, int ny, int nz,
+                           double px, double py, double pz, double g[3])
+{
+    double fx = floor(px), fy = floor(py), fz = floor(pz);
+    double tx = px - fx, ty = py - fy, tz = pz - fz;
+    int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    g[0] = g[1] = g[2] = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double c = v[lin(clampi(ix + dx, nx), clampi(iy + dy, ny), clampi(iz + dz, nz), nx, ny)];
+                double wx = dx ? tx : 1.0 - tx, wy = dy ? ty : 1.0 - ty, wz = dz ? tz : 1.0 - tz;
+                double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+                g[0] += sx * wy * wz * c;
+                g[1] += wx * sy * wz * c;
+                g[2] += wx * wy * sz * c;
+            }
+}
+
+static void trilinear_grad_f(const float* v, int nx, int ny, int nz,
+                             double px, double py, double pz, double g[3])
+{
+    double fx = floor(px), fy = floor(py), fz = floor(pz);
+    double tx = px - fx, ty = py - fy, tz = pz - fz;
+    int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    g[0] = g[1] = g[2] = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double c = (double)v[lin(clampi(ix + dx, nx), clampi(iy + dy, ny), clampi(iz + dz, nz), nx, ny)];
+                double wx = dx ? tx : 1.0 - tx, wy = dy ? ty : 1.0 - ty, wz = dz ? tz : 1.0 - tz;
+                double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+                g[0] += sx * wy * wz * c;
+                g[1] += wx * sy * wz * c;
+                g[2] += wx * wy * sz * c;
+            }
+}
+
+/* m, its patch moments, the static moments and I'_s for the SSD functions. */
+static void ssd_forward(const double* ct, const double* s, const double* r, int nx, int ny, int nz,
+                        int px, int py, int pz, double tau, double* m, double* mu_m, double* var_m,
+                        double* mu_s, double* var_s, double* f)
+{
+    long n = (long)nx * ny * nz;
+    orc_warp(ct, r, nx, ny, nz, m);
+    orc_patch_moments(m, nx, ny, nz, px, py, pz, mu_m, var_m);
+    orc_patch_moments(s, nx, ny, nz, px, py, pz, mu_s, var_s);
+    orc_correct(mu_m, var_m, mu_s, var_s, s, n, tau, NULL, NULL, f);
+}
+
+double orc_ssd_loss(const double* ct, const double* s, const double* r, int nx, int ny, int nz,
+                    int px, int py, int pz, double tau)
+{
+    long n = (long)nx * ny * nz;
+    double* buf = (double*)malloc(sizeof(double) * 6 * n);
+    double *m = buf, *mu_m = buf + n, *var_m = buf + 2 * n, *mu_s = buf + 3 * n, *var_s = buf + 4 * n,
+           *f = buf + 5 * n;
+    ssd_forward(ct, s, r, nx, ny, nz, px, py, pz, tau, m, mu_m, var_m, mu_s, var_s, f);
+    double L = 0.0;
+    for (long i = 0; i < n; ++i) L += (m[i] - f[i]) * (m[i] - f[i]);
+    free(buf);
+    return L;
+}
+
+void orc_ssd_grad(const double* ct, const double* s, const double* r, int nx, int ny, int nz,
+                  int px, int py, int pz, double tau, double* grad)
+{
+    long n = (long)nx * ny * nz;
+    double np = (double)px * py * pz;
+    int rx = px / 2, ry = py / 2, rz = pz / 2;
+    double* buf = (double*)malloc(sizeof(double) * 7 * n);
+    double *m = buf, *mu_m = buf + n, *var_m = buf + 2 * n, *mu_s = buf + 3 * n, *var_s = buf + 4 * n,
+           *f = buf + 5 * n, *G = buf + 6 * n;
+    ssd_forward(ct, s, r, nx, ny, nz, px, py, pz, tau, m, mu_m, var_m, mu_s, var_s, f);
+    for (long i = 0; i < n; ++i) G[i] = 2.0 * (m[i] - f[i]);
+    /* scatter every patch occurrence of every voxel j, literally */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = lin(x, y, z, nx, ny);
+                double D = m[i] - f[i];
+                int flat = !(var_s[i] > tau);
+                double sig = sqrt(var_m[i]);
+                double coef = (!flat && sig > 0.0) ? (s[i] - mu_s[i]) / sqrt(var_s[i]) / (np * sig) : 0.0;
+                for (int k = -rz; k <= rz; ++k)
+                    for (int jj = -ry; jj <= ry; ++jj)
+                        for (int ii = -rx; ii <= rx; ++ii) {
+                            long j = lin(clampi(x + ii, nx), clampi(y + jj, ny), clampi(z + k, nz), nx, ny);
+                            G[j] -= 2.0 * D * (1.0 / np + coef * (m[j] - mu_m[i]));
+                        }
+            }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = lin(x, y, z, nx, ny);
+                double g[3];
+                trilinear_grad(ct, nx, ny, nz, x + r[i], y + r[n + i], z + r[2 * n + i], g);
+                for (int c = 0; c < 3; ++c) grad[c * n + i] = G[i] * g[c];
+            }
+    free(buf);
+}
+
+/* #{k in [-R, R] : clamp(x + k) = j} along one axis of length len. */
+static int clamp_count(int x, int j, int R, int len)
+{
+    int c = 0;
+    for (int k = -R; k <= R; ++k)
+        if (clampi(x + k, len) == j) ++c;
+    return c;
+}
+
+void orc_ssd_grad_pts(const float* ct, const float* s, const float* r, int nx, int ny, int nz,
+                      int px, int py, int pz, double tau, const long* pts, long npts, double* out)
+{
+    long n = (long)nx * ny * nz;
+    double np = (double)px * py * pz;
+    int rx = px / 2, ry = py / 2, rz = pz / 2;
+#pragma omp parallel for schedule(dynamic)
+    for (long q = 0; q < npts; ++q) {
+        int jx, jy, jz;
+        long jl = pts[q];
+        unlin(jl, nx, ny, &jx, &jy, &jz);
+        /* m on the box of radius 2R around j (every value a patch of a patch
+         * around j can touch), from the FP32 CT and field */
+        int bx0 = jx - 2 * rx < 0 ? 0 : jx - 2 * rx, bx1 = jx + 2 * rx > nx - 1 ? nx - 1 : jx + 2 * rx;
+        int by0 = jy - 2 * ry < 0 ? 0 : jy - 2 * ry, by1 = jy + 2 * ry > ny - 1 ? ny - 1 : jy + 2 * ry;
+        int bz0 = jz - 2 * rz < 0 ? 0 : jz - 2 * rz, bz1 = jz + 2 * rz > nz - 1 ? nz - 1 : jz + 2 * rz;
+        int wx = bx1 - bx0 + 1, wy = by1 - by0 + 1, wz = bz1 - bz0 + 1;
+        double* mb = (double*)malloc(sizeof(double) * wx * wy * wz);
+        for (int z = bz0; z <= bz1; ++z)
+            for (int y = by0; y <= by1; ++y)
+                for (int x = bx0; x <= bx1; ++x) {
+                    long i = lin(x, y, z, nx, ny);
+                    mb[((long)(z - bz0) * wy + (y - by0)) * wx + (x - bx0)] =
+                        trilinear_f(ct, nx, ny, nz, x + (double)r[i], y + (double)r[n + i], z + (double)r[2 * n + i]);
+                }
+#define MB(X, Y, Z) mb[((long)((Z) - bz0) * wy + ((Y) - by0)) * wx + ((X) - bx0)]
+        double mj = MB(jx, jy, jz);
+        double G = 0.0;
+        for (int z = jz - rz; z <= jz + rz; ++z)
+            for (int y = jy - ry; y <= jy + ry; ++y)
+                for (int x = jx - rx; x <= jx + rx; ++x) {
+                    if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) continue;
+                    int mult = clamp_count(x, jx, rx, nx) * clamp_count(y, jy, ry, ny) * clamp_count(z, jz, rz, nz);
+                    if (mult == 0 && !(x == jx && y == jy && z == jz)) continue;
+                    /* moments of m (two-pass) and of s at x */
+                    double sm = 0.0;
+                    for (int k = -rz; k <= rz; ++k)
+                        for (int jj = -ry; jj <= ry; ++jj)
+                            for (int ii = -rx; ii <= rx; ++ii)
+                                sm += MB(clampi(x + ii, nx), clampi(y + jj, ny), clampi(z + k, nz));
+                    double mu = sm / np, qm = 0.0;
+                    for (int k = -rz; k <= rz; ++k)
+                        for (int jj = -ry; jj <= ry; ++jj)
+                            for (int ii = -rx; ii <= rx; ++ii) {
+                                double d = MB(clampi(x + ii, nx), clampi(y + jj, ny), clampi(z + k, nz)) - mu;
+                                qm += d * d;
+                            }
+                    double var = qm / np, mu_s, var_s, a, b;
+                    patch_at_f(s, nx, ny, nz, px, py, pz, x, y, z, &mu_s, &var_s);
+                    match_moments(mu, var, mu_s, var_s, tau, &a, &b);
+                    long i = lin(x, y, z, nx, ny);
+                    double D = MB(x, y, z) - (a * (double)s[i] + b);
+                    if (x == jx && y == jy && z == jz) G += 2.0 * D;
+                    int flat = !(var_s > tau);
+                    double sig = sqrt(var);
+                    double coef = (!flat && sig > 0.0) ? ((double)s[i] - mu_s) / sqrt(var_s) / (np * sig) : 0.0;
+                    G -= 2.0 * D * mult * (1.0 / np + coef * (mj - mu));
+                }
+#undef MB
+        free(mb);
+        double g[3];
+        trilinear_grad_f(ct, nx, ny, nz, jx + (double)r[jl], jy + (double)r[n + jl], jz + (double)r[2 * n + jl], g);
+        for (int c = 0; c < 3; ++c) out[3 * q + c] = G * g[c];
+    }
+}

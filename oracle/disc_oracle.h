@@ -17,8 +17,9 @@
  * precision a GPU stores) and promote every value to FP64 on load.
  *
  * Parity status: every function here is pinned by the CPU test-suite
- * (library routines, closed forms, invariants, brute force). The Eq. 7-10
- * mask/fill and the stopping criterion are not part of this oracle.
+ * (library routines, closed forms, invariants, brute force, and central
+ * finite differences for the SSD gradient). The Eq. 7-10 mask/fill and the
+ * stopping criterion are not part of this oracle.
  */
 #ifndef DISC_ORACLE_H
 #define DISC_ORACLE_H
@@ -119,6 +120,22 @@ void orc_force_pts(const float* m, const float* f, const float* r,
 /* Gaussian of the FP32 field rt at the listed voxels; out is [npts][3]. */
 void orc_gauss_pts(const float* rt, int nx, int ny, int nz, double sigma,
                    const long* pts, long npts, double* out);
+
+/* ---- differentiable DISC: SSD between m = warp(ct, r) and I'_s ---------- */
+
+/* L = sum_x (m(x) - I'_s(x))^2, I'_s from the patch moments of m and of the
+ * static image s (Eq. 3-6, flat static patch: a = 1). */
+double orc_ssd_loss(const double* ct, const double* s, const double* r, int nx, int ny, int nz,
+                    int px, int py, int pz, double tau);
+
+/* dL/dr [3][N], analytic (chain rule through Eq. 3-6 and the trilinear warp),
+ * by a literal scatter over every clamped patch occurrence. */
+void orc_ssd_grad(const double* ct, const double* s, const double* r, int nx, int ny, int nz,
+                  int px, int py, int pz, double tau, double* grad);
+
+/* dL/dr at the listed voxels from FP32 ct, s and r; out is [npts][3]. */
+void orc_ssd_grad_pts(const float* ct, const float* s, const float* r, int nx, int ny, int nz,
+                      int px, int py, int pz, double tau, const long* pts, long npts, double* out);
 
 #ifdef __cplusplus
 }

@@ -405,3 +405,79 @@ def test_point_evaluators_agree_with_whole_volume():
     got = oracle.gauss_pts(rt32, 1.5, pts)
     for c in range(3):
         np.testing.assert_allclose(got[:, c], gs[c].ravel()[pts], atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Differentiable DISC: SSD between m = warp(CT, r) and I'_s (Eq. 3-6)
+# --------------------------------------------------------------------------
+
+def _ssd_case(shape, seed):
+    g = rng(seed)
+    ct = g.normal(0.0, 100.0, shape).cumsum(axis=2)
+    s = 0.8 * ct + g.normal(0.0, 20.0, shape) + 50.0
+    # fractional parts kept away from 0 and 1 so that +-eps never crosses a
+    # cell of the piecewise-trilinear warp
+    r = np.floor(g.uniform(-1.5, 1.5, (3,) + shape)) + g.uniform(0.2, 0.8, (3,) + shape)
+    return ct, s, r
+
+
+@pytest.mark.parametrize("patch", [(3, 3, 3), (5, 3, 1), (9, 9, 9), (1, 3, 5)])
+def test_ssd_gradient_vs_finite_differences(patch):
+    """The analytic dL/dr equals central differences of the oracle's own loss
+    at every coordinate of a small, edge-dominated volume (every patch is
+    clamped somewhere), and the FD error falls as eps^2 (so it is truncation,
+    not a wrong term)."""
+    ct, s, r = _ssd_case((5, 6, 7), 3)
+    g = oracle.ssd_grad(ct, s, r, patch)
+    errs = []
+    for eps in (1e-3, 1e-4):
+        fd = np.zeros_like(r)
+        for idx in np.ndindex(r.shape):
+            rp = r.copy()
+            rm = r.copy()
+            rp[idx] += eps
+            rm[idx] -= eps
+            fd[idx] = (oracle.ssd_loss(ct, s, rp, patch) - oracle.ssd_loss(ct, s, rm, patch)) / (2 * eps)
+        errs.append(np.abs(g - fd).max() / np.abs(fd).max())
+    assert errs[0] < 1e-5
+    assert errs[1] < errs[0] / 30.0
+
+
+def test_ssd_minimum_at_consistent_images():
+    """S = CT or S = alpha CT + beta at r = 0: I'_s = m everywhere, so L = 0
+    and the gradient vanishes (a minimum)."""
+    g = rng(4)
+    ct = g.normal(0.0, 200.0, (6, 7, 8)).cumsum(axis=1)
+    r = np.zeros((3,) + ct.shape)
+    for s in (ct.copy(), 1.7 * ct - 300.0):
+        assert oracle.ssd_loss(ct, s, r, (3, 3, 3)) < 1e-16 * (ct * ct).sum()
+        gr = oracle.ssd_grad(ct, s, r, (3, 3, 3))
+        assert np.abs(gr).max() < 1e-9 * np.abs(ct).max()
+
+
+def test_ssd_flat_patches_and_unit_patch():
+    """A 1x1x1 patch makes every static patch flat (a = 1, I'_s = m): L = 0
+    and gradient 0 up to rounding. A constant static image makes I'_s = E(M): L is the sum of
+    squared deviations of m from its patch mean, checked against scipy."""
+    ct, s, r = _ssd_case((4, 5, 6), 5)
+    # I'_s = s + (m - s) equals m up to one rounding
+    scale = np.abs(ct).max()
+    assert oracle.ssd_loss(ct, s, r, (1, 1, 1)) <= ct.size * (1e-15 * scale) ** 2
+    assert np.abs(oracle.ssd_grad(ct, s, r, (1, 1, 1))).max() <= 1e-12 * scale * scale
+    flat = np.full(ct.shape, 40.0)
+    m = oracle.warp(ct, r)
+    mu = ndi.uniform_filter(m, size=(3, 3, 3), mode="nearest")
+    ref = ((m - mu) ** 2).sum()
+    assert abs(oracle.ssd_loss(ct, flat, r, (3, 3, 3)) - ref) <= 1e-10 * ref
+
+
+def test_ssd_gradient_point_evaluator():
+    """The point evaluator (FP32 state, local recomputation of moments)
+    equals the whole-volume gradient on the same FP32-rounded inputs."""
+    ct, s, r = _ssd_case((6, 7, 9), 6)
+    ct32, s32, r32 = (a.astype(np.float32) for a in (ct, s, r))
+    for patch in ((3, 3, 3), (5, 3, 1), (9, 9, 9)):
+        g = oracle.ssd_grad(ct32.astype(np.float64), s32.astype(np.float64), r32.astype(np.float64), patch)
+        pts = np.arange(ct.size)
+        gp = oracle.ssd_grad_pts(ct32, s32, r32, patch, pts)
+        assert np.abs(gp.T.reshape(g.shape) - g).max() <= 1e-12 * np.abs(g).max()
