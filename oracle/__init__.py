@@ -24,6 +24,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _D = ctypes.POINTER(ctypes.c_double)
 _F = ctypes.POINTER(ctypes.c_float)
 _L = ctypes.POINTER(ctypes.c_long)
+_IP = ctypes.POINTER(ctypes.c_int)
 _I = ctypes.c_int
 
 
@@ -38,11 +39,14 @@ class Params(ctypes.Structure):
         ("global_shift", ctypes.c_int),
         ("var_floor", ctypes.c_double),
         ("diff_floor", ctypes.c_double),
+        ("force_mode", ctypes.c_int),
+        ("stop_eps", ctypes.c_double),
+        ("stop_lag", ctypes.c_int),
     ]
 
 
 def make_params(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,), global_shift=True,
-                var_floor=1e-2, diff_floor=1e-3):
+                var_floor=1e-2, diff_floor=1e-3, force_mode=0, stop_eps=0.0, stop_lag=10):
     p = Params()
     for d in range(3):
         p.patch[d] = int(patch[d])
@@ -53,6 +57,9 @@ def make_params(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,), global_shift=
     p.global_shift = 1 if global_shift else 0
     p.var_floor = float(var_floor)
     p.diff_floor = float(diff_floor)
+    p.force_mode = int(force_mode)
+    p.stop_eps = float(stop_eps)
+    p.stop_lag = int(stop_lag)
     return p
 
 
@@ -95,6 +102,9 @@ def lib():
         L.orc_correct_pts.argtypes = [_F, _F, _I, _I, _I, _I, _I, _I, ctypes.c_double, _L, ctypes.c_long, _D]
         L.orc_force_pts.argtypes = [_F, _F, _F, _I, _I, _I, ctypes.c_double, _L, ctypes.c_long, _D]
         L.orc_gauss_pts.argtypes = [_F, _I, _I, _I, ctypes.c_double, _L, ctypes.c_long, _D]
+        L.orc_force_double.argtypes = [_D, _D, _I, _I, _I, ctypes.c_double, _D]
+        L.orc_register_ex.restype = ctypes.c_int
+        L.orc_register_ex.argtypes = [_D, _D, _I, _I, _I, ctypes.POINTER(Params), _D, _D, _IP, _D, _I]
         L.orc_ssd_loss.restype = ctypes.c_double
         L.orc_ssd_loss.argtypes = [_D, _D, _D, _I, _I, _I, _I, _I, _I, ctypes.c_double]
         L.orc_ssd_grad.argtypes = [_D, _D, _D, _I, _I, _I, _I, _I, _I, ctypes.c_double, _D]
@@ -194,6 +204,16 @@ def force(m, f, eps_d=1e-3):
     return u
 
 
+def force_double(m, f, eps_d=1e-3):
+    """Both terms of Eq. 1 (double force)."""
+    m, pm = _d(m)
+    f, pf = _d(f)
+    nx, ny, nz = _dims(m)
+    u = np.empty((3,) + m.shape)
+    lib().orc_force_double(pm, pf, nx, ny, nz, float(eps_d), u.ctypes.data_as(_D))
+    return u
+
+
 def gauss_taps(sigma):
     w = np.zeros(129)
     R = lib().orc_gauss_taps(float(sigma), w.ctypes.data_as(_D))
@@ -241,6 +261,25 @@ def register(ct, cbct, params):
     if rc != 0:
         raise ValueError("orc_register rejected its arguments")
     return r, f
+
+
+def register_ex(ct, cbct, params):
+    """Algorithm A1 with the Sec. 2.3 stopping rule (params.stop_eps > 0).
+    Returns (r, I'_s, iterations run per level, l^(k) per level)."""
+    ct, pc = _d(ct)
+    cb, pb = _d(cbct)
+    nx, ny, nz = _dims(ct)
+    r = np.empty((3,) + ct.shape)
+    f = np.empty_like(ct)
+    done = (ctypes.c_int * 8)()
+    stride = max(1, max(int(params.iters[l]) for l in range(params.levels)))
+    hist = np.full((params.levels, stride), np.nan)
+    rc = lib().orc_register_ex(pc, pb, nx, ny, nz, ctypes.byref(params), r.ctypes.data_as(_D),
+                               f.ctypes.data_as(_D), done, hist.ctypes.data_as(_D), stride)
+    if rc != 0:
+        raise ValueError("orc_register_ex rejected its arguments")
+    n = [int(done[l]) for l in range(params.levels)]
+    return r, f, n, [hist[l, :n[l]].copy() for l in range(params.levels)]
 
 
 def _pts(pts):

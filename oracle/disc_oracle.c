@@ -269,6 +269,39 @@ void orc_force(const double* m, const double* f, int nx, int ny, int nz,
             }
 }
 
+/* Eq. 1 first term plus its second (moving-gradient) term. */
+void orc_force_double(const double* m, const double* f, int nx, int ny, int nz,
+                      double eps_d, double* u)
+{
+    long n = (long)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = lin(x, y, z, nx, ny);
+                double d = m[i] - f[i];
+                double g[2][3];
+                const double* img[2] = {f, m};
+                for (int t = 0; t < 2; ++t) {
+                    const double* v = img[t];
+                    g[t][0] = (v[lin(clampi(x + 1, nx), y, z, nx, ny)] - v[lin(clampi(x - 1, nx), y, z, nx, ny)]) / 2.0;
+                    g[t][1] = (v[lin(x, clampi(y + 1, ny), z, nx, ny)] - v[lin(x, clampi(y - 1, ny), z, nx, ny)]) / 2.0;
+                    g[t][2] = (v[lin(x, y, clampi(z + 1, nz), nx, ny)] - v[lin(x, y, clampi(z - 1, nz), nx, ny)]) / 2.0;
+                }
+                double uu[3] = {0.0, 0.0, 0.0};
+                if (fabs(d) >= eps_d) {
+                    for (int t = 0; t < 2; ++t) {
+                        double den = g[t][0] * g[t][0] + g[t][1] * g[t][1] + g[t][2] * g[t][2] + d * d;
+                        if (den > 0.0)
+                            for (int c = 0; c < 3; ++c) uu[c] += d * g[t][c] / den;
+                    }
+                }
+                u[i] = uu[0];
+                u[n + i] = uu[1];
+                u[2 * n + i] = uu[2];
+            }
+}
+
 int orc_gauss_taps(double sigma, double* w)
 {
     if (!(sigma > 0.0)) return -1;
@@ -338,7 +371,10 @@ void orc_iterate(const double* ct, const double* s, const double* mu_s,
     orc_patch_moments(m, nx, ny, nz, p->patch[0], p->patch[1], p->patch[2], mu_m, var_m);
     orc_correct(mu_m, var_m, mu_s, var_s, s, n, p->var_floor, NULL, NULL, f);
     /* A1 step 4: Eq. 1 force on I'_s; step 5: add dr = -u to r */
-    orc_force(m, f, nx, ny, nz, p->diff_floor, u);
+    if (p->force_mode == 1)
+        orc_force_double(m, f, nx, ny, nz, p->diff_floor, u);
+    else
+        orc_force(m, f, nx, ny, nz, p->diff_floor, u);
     for (long i = 0; i < 3 * n; ++i) r[i] -= u[i];
     if (rt_out) memcpy(rt_out, r, sizeof(double) * 3 * n);
     /* A1 step 6: Gaussian on each component of r */
@@ -357,6 +393,22 @@ void orc_iterate(const double* ct, const double* s, const double* mu_s,
 
 int orc_register(const double* ct, const double* cbct0, int nx, int ny, int nz,
                  const orc_params* p, double* r_out, double* f_out)
+{
+    int done[8];
+    return orc_register_ex(ct, cbct0, nx, ny, nz, p, r_out, f_out, done, NULL, 0);
+}
+
+/* Sum over voxels of the Euclidean norm of a field [3][n]. */
+static double field_norm_sum(const double* v, long n)
+{
+    double s = 0.0;
+    for (long i = 0; i < n; ++i) s += sqrt(v[i] * v[i] + v[n + i] * v[n + i] + v[2 * n + i] * v[2 * n + i]);
+    return s;
+}
+
+int orc_register_ex(const double* ct, const double* cbct0, int nx, int ny, int nz,
+                    const orc_params* p, double* r_out, double* f_out, int* iters_done,
+                    double* l_hist, int hist_stride)
 {
     if (!ct || !cbct0 || !p || !r_out || nx < 1 || ny < 1 || nz < 1) return -1;
     if (p->levels < 1 || p->levels > 8 || !(p->sigma > 0.0)) return -1;
@@ -413,8 +465,32 @@ int orc_register(const double* ct, const double* cbct0, int nx, int ny, int nz,
         free(f);
         f = (double*)malloc(sizeof(double) * ns[l]);
         for (long i = 0; i < ns[l]; ++i) f[i] = ss[l][i];
-        for (int k = 0; k < p->iters[l]; ++k)
-            orc_iterate(cts[l], ss[l], mu_s, var_s, r, lx, ly, lz, p, NULL, f, NULL);
+        int k_done = 0;
+        if (p->stop_eps > 0.0) {
+            /* Sec. 2.3 stopping rule on l^(k) = sum |dr^(k+1)| / sum |r^(k)| */
+            long nl = ns[l];
+            double* r_prev = (double*)malloc(sizeof(double) * 3 * nl);
+            double* dr = (double*)malloc(sizeof(double) * 3 * nl);
+            double* hist = (double*)malloc(sizeof(double) * (p->iters[l] > 0 ? p->iters[l] : 1));
+            for (int k = 0; k < p->iters[l]; ++k) {
+                memcpy(r_prev, r, sizeof(double) * 3 * nl);
+                orc_iterate(cts[l], ss[l], mu_s, var_s, r, lx, ly, lz, p, NULL, f, NULL);
+                for (long i = 0; i < 3 * nl; ++i) dr[i] = r[i] - r_prev[i];
+                double num = field_norm_sum(dr, nl), den = field_norm_sum(r_prev, nl);
+                hist[k] = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+                if (l_hist) l_hist[(long)l * hist_stride + k] = hist[k];
+                k_done = k + 1;
+                if (k >= p->stop_lag && hist[k - p->stop_lag] - hist[k] <= p->stop_eps) break;
+            }
+            free(r_prev);
+            free(dr);
+            free(hist);
+        } else {
+            for (int k = 0; k < p->iters[l]; ++k)
+                orc_iterate(cts[l], ss[l], mu_s, var_s, r, lx, ly, lz, p, NULL, f, NULL);
+            k_done = p->iters[l];
+        }
+        if (iters_done) iters_done[l] = k_done;
         free(mu_s);
         free(var_s);
     }

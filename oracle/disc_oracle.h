@@ -18,8 +18,9 @@
  *
  * Parity status: every function here is pinned by the CPU test-suite
  * (library routines, closed forms, invariants, brute force, and central
- * finite differences for the SSD gradient). The Eq. 7-10 mask/fill and the
- * stopping criterion are not part of this oracle.
+ * finite differences for the SSD gradient, closed forms of the double
+ * force and of the stopping rule). The Eq. 7-10 mask/fill is not part of
+ * this oracle.
  */
 #ifndef DISC_ORACLE_H
 #define DISC_ORACLE_H
@@ -36,6 +37,9 @@ typedef struct {
     int    global_shift; /* 1: shift CBCT by the mean difference (Sec. 2.3) */
     double var_floor;    /* tau: a static-patch variance <= tau counts as flat (a := 1) */
     double diff_floor;   /* eps_d: |m - f'| < eps_d gives a zero force */
+    int    force_mode;   /* 0: Eq. 1 static-gradient term; 1: both terms of Eq. 1 */
+    double stop_eps;     /* > 0: Sec. 2.3 stopping rule with this epsilon; iters[] caps */
+    int    stop_lag;     /* the rule compares l^(k - lag) with l^(k) (10 in Sec. 2.3) */
 } orc_params;
 
 /* Number of OpenMP threads the whole-volume functions use. */
@@ -79,6 +83,12 @@ void orc_correct(const double* mu_m, const double* var_m,
 void orc_force(const double* m, const double* f, int nx, int ny, int nz,
                double eps_d, double* u);
 
+/* Both terms of Eq. 1 (double force): u = d grad f / (|grad f|^2 + d^2)
+ * + d grad m / (|grad m|^2 + d^2), d = m - f; each term 0 where its
+ * denominator is 0, both 0 where |d| < eps_d. */
+void orc_force_double(const double* m, const double* f, int nx, int ny, int nz,
+                      double eps_d, double* u);
+
 /* Truncated, normalised Gaussian taps w[0..2R], R = ceil(3 sigma).
  * Returns R (<= 64) or -1 when sigma is not positive. */
 int orc_gauss_taps(double sigma, double* w);
@@ -100,6 +110,17 @@ void orc_iterate(const double* ct, const double* s, const double* mu_s,
  * on invalid arguments. */
 int orc_register(const double* ct, const double* cbct0, int nx, int ny, int nz,
                  const orc_params* p, double* r_out, double* f_out);
+
+/* orc_register with the Sec. 2.3 stopping rule when p->stop_eps > 0: per
+ * level, after iteration k (0-based) l^(k) = sum_x |r^(k+1) - r^(k)| /
+ * sum_x |r^(k)| (Euclidean norm per voxel; 0 when both sums are 0, +inf
+ * when only the denominator is), and the level ends once k >= lag and
+ * l^(k - lag) - l^(k) <= eps, or after iters[level] iterations.
+ * iters_done[level] receives the count run; l_hist (may be NULL) receives
+ * l^(k) at l_hist[level * hist_stride + k]. */
+int orc_register_ex(const double* ct, const double* cbct0, int nx, int ny, int nz,
+                    const orc_params* p, double* r_out, double* f_out, int* iters_done,
+                    double* l_hist, int hist_stride);
 
 /* ---- point evaluators on FP32 state (sampled parity at full size) ------ */
 

@@ -481,3 +481,73 @@ def test_ssd_gradient_point_evaluator():
         pts = np.arange(ct.size)
         gp = oracle.ssd_grad_pts(ct32, s32, r32, patch, pts)
         assert np.abs(gp.T.reshape(g.shape) - g).max() <= 1e-12 * np.abs(g).max()
+
+
+# --------------------------------------------------------------------------
+# Eq. 1 double force and the Sec. 2.3 stopping rule
+# --------------------------------------------------------------------------
+
+def test_double_force_closed_form_on_linear_images():
+    """f = alpha x, m = beta x + c: both gradients are constant along x in the
+    interior, so u_x = d alpha / (alpha^2 + d^2) + d beta / (beta^2 + d^2)
+    with d = m - f, and u_y = u_z = 0 there."""
+    shape = (5, 6, 12)
+    x = np.broadcast_to(np.arange(shape[2], dtype=np.float64), shape)
+    for alpha, beta, c in ((3.0, 2.0, 7.0), (-1.5, 4.0, -2.0), (2.0, 2.0, 0.5)):
+        f = alpha * x
+        m = beta * x + c
+        u = oracle.force_double(m, f, 0.0)
+        d = m - f
+        ref = d * alpha / (alpha ** 2 + d ** 2) + d * beta / (beta ** 2 + d ** 2)
+        inner = (slice(None), slice(None), slice(1, -1))
+        assert np.allclose(u[0][inner], ref[inner], rtol=1e-13, atol=1e-15)
+        assert np.abs(u[1:]).max() == 0.0
+
+
+def test_double_force_is_static_term_minus_swapped_term():
+    """The moving-gradient term of Eq. 1 is the static-gradient term with the
+    images' roles swapped and the sign of d reversed, so
+    force_double(m, f) = force(m, f) - force(f, m) voxel by voxel; and both
+    vanish on identical images."""
+    g = rng(8)
+    m = g.normal(0.0, 200.0, (7, 8, 9)).cumsum(axis=0)
+    f = m + g.normal(0.0, 30.0, m.shape)
+    for eps in (0.0, 1e-3, 5.0):
+        u = oracle.force_double(m, f, eps)
+        ref = oracle.force(m, f, eps) - oracle.force(f, m, eps)
+        assert np.allclose(u, ref, rtol=1e-12, atol=1e-14)
+    assert np.abs(oracle.force_double(m, m.copy(), 1e-3)).max() == 0.0
+
+
+def test_stopping_rule():
+    """l^(k) is the definition written out (two fixed-count runs of the
+    oracle give r^(k) and r^(k+1)); the level ends at the first k >= lag with
+    l^(k-lag) - l^(k) <= eps; identical images stop right at k = lag; a
+    non-positive eps keeps the fixed counts."""
+    from synth.phantom import make_ellipsoid_pair
+
+    c = make_ellipsoid_pair((20, 22, 24), pair=5)
+    ct, cb = c.ct.astype(np.float64), c.cbct.astype(np.float64)
+    lag, K = 3, 14
+    # full history with a rule that never fires
+    p_all = oracle.make_params(patch=(3, 3, 3), iters=(K,), stop_eps=1e-300, stop_lag=lag)
+    _, _, n_all, h_all = oracle.register_ex(ct, cb, p_all)
+    h = h_all[0]
+    assert n_all == [K] and np.isinf(h[0])
+    for k in (1, 5, 9):
+        rk, _ = oracle.register(ct, cb, oracle.make_params(patch=(3, 3, 3), iters=(k,)))
+        rk1, _ = oracle.register(ct, cb, oracle.make_params(patch=(3, 3, 3), iters=(k + 1,)))
+        num = np.sqrt(((rk1 - rk) ** 2).sum(axis=0)).sum()
+        den = np.sqrt((rk ** 2).sum(axis=0)).sum()
+        assert abs(h[k] - num / den) <= 1e-12 * num / den
+    drops = h[:-lag] - h[lag:]  # l^(k - lag) - l^(k) for k = lag .. K-1
+    eps = float(np.median(drops[np.isfinite(drops)]))
+    first = next(k for k in range(lag, K) if h[k - lag] - h[k] <= eps)
+    _, _, n, hh = oracle.register_ex(ct, cb, oracle.make_params(patch=(3, 3, 3), iters=(K,), stop_eps=eps,
+                                                                 stop_lag=lag))
+    assert n == [first + 1] and np.array_equal(hh[0], h[:first + 1])
+    _, _, n_id, h_id = oracle.register_ex(ct, ct.copy(), oracle.make_params(
+        patch=(3, 3, 3), iters=(K,), stop_eps=1e-4, stop_lag=lag))
+    assert n_id == [lag + 1] and np.all(h_id[0] == 0.0)
+    _, _, n_off, _ = oracle.register_ex(ct, cb, oracle.make_params(patch=(3, 3, 3), iters=(K,), stop_eps=0.0))
+    assert n_off == [K]
