@@ -42,11 +42,19 @@ class Params(ctypes.Structure):
         ("force_mode", ctypes.c_int),
         ("stop_eps", ctypes.c_double),
         ("stop_lag", ctypes.c_int),
+        ("mask_mode", ctypes.c_int),
+        ("hu0", ctypes.c_double),
+        ("a_lo", ctypes.c_double),
+        ("a_hi", ctypes.c_double),
+        ("fill_h", ctypes.c_double),
+        ("fill_t", ctypes.c_int * 3),
+        ("fill_passes", ctypes.c_int),
     ]
 
 
 def make_params(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,), global_shift=True,
-                var_floor=1e-2, diff_floor=1e-3, force_mode=0, stop_eps=0.0, stop_lag=10):
+                var_floor=1e-2, diff_floor=1e-3, force_mode=0, stop_eps=0.0, stop_lag=10, mask_mode=0,
+                hu0=0.0, a_lo=0.5, a_hi=1.5, fill_h=0.0, fill_t=(7, 7, 3), fill_passes=10):
     p = Params()
     for d in range(3):
         p.patch[d] = int(patch[d])
@@ -60,6 +68,14 @@ def make_params(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,), global_shift=
     p.force_mode = int(force_mode)
     p.stop_eps = float(stop_eps)
     p.stop_lag = int(stop_lag)
+    p.mask_mode = int(mask_mode)
+    p.hu0 = float(hu0)
+    p.a_lo = float(a_lo)
+    p.a_hi = float(a_hi)
+    p.fill_h = float(fill_h)
+    for d in range(3):
+        p.fill_t[d] = int(fill_t[d])
+    p.fill_passes = int(fill_passes)
     return p
 
 
@@ -103,6 +119,14 @@ def lib():
         L.orc_force_pts.argtypes = [_F, _F, _F, _I, _I, _I, ctypes.c_double, _L, ctypes.c_long, _D]
         L.orc_gauss_pts.argtypes = [_F, _I, _I, _I, ctypes.c_double, _L, ctypes.c_long, _D]
         L.orc_force_double.argtypes = [_D, _D, _I, _I, _I, ctypes.c_double, _D]
+        _U8 = ctypes.POINTER(ctypes.c_ubyte)
+        L.orc_fill.restype = ctypes.c_int
+        L.orc_fill.argtypes = [_D, _D, _U8, _D, _I, _I, _I, ctypes.c_double, _IP, _I, _D, _D]
+        L.orc_mask_fill.restype = ctypes.c_int
+        L.orc_mask_fill.argtypes = [_D, _D, _D, _D, _D, _D, _I, _I, _I, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, _IP, _I, _D, _D, _U8]
+        L.orc_a_median.restype = ctypes.c_double
+        L.orc_a_median.argtypes = [_D, _D, _I, _I, _I, _I, _I, _I, ctypes.c_double]
         L.orc_register_ex.restype = ctypes.c_int
         L.orc_register_ex.argtypes = [_D, _D, _I, _I, _I, ctypes.POINTER(Params), _D, _D, _IP, _D, _I]
         L.orc_ssd_loss.restype = ctypes.c_double
@@ -361,3 +385,44 @@ def ssd_grad_pts(ct, s, r, patch, pts, tau=1e-2):
     lib().orc_ssd_grad_pts(pc, ps, pr, nx, ny, nz, int(patch[0]), int(patch[1]), int(patch[2]),
                            float(tau), pts.ctypes.data_as(_L), len(pts), out.ctypes.data_as(_D))
     return out
+
+
+def fill(a0, b0, valid0, s, h, t=(7, 7, 3), passes=10):
+    """Eq. 8-10 fill from (a0, b0) with initial validity valid0 (bool).
+    Returns (A, B, passes that filled something)."""
+    a0, pa = _d(a0)
+    b0, pb = _d(b0)
+    s, ps = _d(s)
+    v = np.ascontiguousarray(valid0, dtype=np.uint8)
+    nx, ny, nz = _dims(s)
+    A = np.empty_like(s)
+    B = np.empty_like(s)
+    tt = (ctypes.c_int * 3)(*[int(x) for x in t])
+    used = lib().orc_fill(pa, pb, v.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), ps, nx, ny, nz, float(h), tt,
+                          int(passes), A.ctypes.data_as(_D), B.ctypes.data_as(_D))
+    return A, B, used
+
+
+def mask_fill(m, s, patch, tau, hu0, a_min, a_max, h, t=(7, 7, 3), passes=10):
+    """Eq. 5-10 at one level: returns (A, B, xi, passes used)."""
+    m, pm = _d(m)
+    s, ps = _d(s)
+    nx, ny, nz = _dims(m)
+    mu_m, var_m = patch_moments(m, patch)
+    mu_s, var_s = patch_moments(s, patch)
+    A = np.empty_like(m)
+    B = np.empty_like(m)
+    xi = np.empty(m.shape, dtype=np.uint8)
+    tt = (ctypes.c_int * 3)(*[int(x) for x in t])
+    used = lib().orc_mask_fill(pm, ps, _d(mu_m)[1], _d(var_m)[1], _d(mu_s)[1], _d(var_s)[1], nx, ny, nz,
+                               float(tau), float(hu0), float(a_min), float(a_max), float(h), tt, int(passes),
+                               A.ctypes.data_as(_D), B.ctypes.data_as(_D),
+                               xi.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    return A, B, xi.astype(bool), used
+
+
+def a_median(ct, s, patch, tau=1e-2):
+    ct, pc = _d(ct)
+    s, ps = _d(s)
+    nx, ny, nz = _dims(ct)
+    return lib().orc_a_median(pc, ps, nx, ny, nz, int(patch[0]), int(patch[1]), int(patch[2]), float(tau))

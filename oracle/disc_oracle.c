@@ -302,6 +302,127 @@ void orc_force_double(const double* m, const double* f, int nx, int ny, int nz,
             }
 }
 
+/* ---- Eq. 7-10: mask and fill ------------------------------------------------ */
+
+int orc_fill(const double* a0, const double* b0, const unsigned char* valid0, const double* s,
+             int nx, int ny, int nz, double h, const int t[3], int passes, double* A, double* B)
+{
+    long n = (long)nx * ny * nz;
+    int tx = t[0] / 2, ty = t[1] / 2, tz = t[2] / 2;
+    unsigned char* valid = (unsigned char*)malloc(n);
+    unsigned char* nvalid = (unsigned char*)malloc(n);
+    double* nA = (double*)malloc(sizeof(double) * n);
+    double* nB = (double*)malloc(sizeof(double) * n);
+    for (long i = 0; i < n; ++i) {
+        valid[i] = valid0[i] ? 1 : 0;
+        /* Eq. 7 paragraph: masked voxels start from a = b = 0 */
+        A[i] = valid[i] ? a0[i] : 0.0;
+        B[i] = valid[i] ? b0[i] : 0.0;
+    }
+    int used = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+        long left = 0;
+        for (long i = 0; i < n; ++i) left += !valid[i];
+        if (left == 0) break;
+        long filled = 0;
+#pragma omp parallel for schedule(static) reduction(+ : filled)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    long i = lin(x, y, z, nx, ny);
+                    nA[i] = A[i];
+                    nB[i] = B[i];
+                    nvalid[i] = valid[i];
+                    if (valid[i]) continue;
+                    double sw = 0.0, sa = 0.0, sb = 0.0;
+                    for (int k = -tz; k <= tz; ++k)
+                        for (int jj = -ty; jj <= ty; ++jj)
+                            for (int ii = -tx; ii <= tx; ++ii) {
+                                int xx = x + ii, yy = y + jj, zz = z + k;
+                                if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+                                long q = lin(xx, yy, zz, nx, ny);
+                                if (!valid[q]) continue;
+                                double ds = s[q] - s[i];
+                                double w = exp(-(ds * ds) / (h * h));
+                                sw += w;
+                                sa += w * A[q];
+                                sb += w * B[q];
+                            }
+                    if (sw > 0.0) {
+                        nA[i] = sa / sw;
+                        nB[i] = sb / sw;
+                        nvalid[i] = 1;
+                        filled += 1;
+                    }
+                }
+        memcpy(A, nA, sizeof(double) * n);
+        memcpy(B, nB, sizeof(double) * n);
+        memcpy(valid, nvalid, n);
+        if (filled == 0) break;
+        used = pass + 1;
+    }
+    /* leftover rule: a voxel never filled keeps its Eq. 5-6 values */
+    for (long i = 0; i < n; ++i)
+        if (!valid[i]) {
+            A[i] = a0[i];
+            B[i] = b0[i];
+        }
+    free(valid);
+    free(nvalid);
+    free(nA);
+    free(nB);
+    return used;
+}
+
+int orc_mask_fill(const double* m, const double* s, const double* mu_m, const double* var_m,
+                  const double* mu_s, const double* var_s, int nx, int ny, int nz, double tau,
+                  double hu0, double a_min, double a_max, double h, const int t[3], int passes,
+                  double* A, double* B, unsigned char* xi)
+{
+    long n = (long)nx * ny * nz;
+    double* a0 = (double*)malloc(sizeof(double) * n);
+    double* b0 = (double*)malloc(sizeof(double) * n);
+    unsigned char* valid = (unsigned char*)malloc(n);
+    for (long i = 0; i < n; ++i) {
+        match_moments(mu_m[i], var_m[i], mu_s[i], var_s[i], tau, &a0[i], &b0[i]);
+        /* Eq. 7 */
+        int masked = fabs(m[i] - s[i]) > hu0 || a0[i] < a_min || a0[i] > a_max;
+        valid[i] = !masked;
+        if (xi) xi[i] = (unsigned char)masked;
+    }
+    int used = orc_fill(a0, b0, valid, s, nx, ny, nz, h, t, passes, A, B);
+    free(a0);
+    free(b0);
+    free(valid);
+    return used;
+}
+
+static int cmp_double(const void* x, const void* y)
+{
+    double a = *(const double*)x, b = *(const double*)y;
+    return (a > b) - (a < b);
+}
+
+double orc_a_median(const double* ct, const double* s, int nx, int ny, int nz, int px, int py, int pz,
+                    double tau)
+{
+    long n = (long)nx * ny * nz;
+    double* buf = (double*)malloc(sizeof(double) * 4 * n);
+    double *mu_m = buf, *var_m = buf + n, *mu_s = buf + 2 * n, *var_s = buf + 3 * n;
+    orc_patch_moments(ct, nx, ny, nz, px, py, pz, mu_m, var_m);
+    orc_patch_moments(s, nx, ny, nz, px, py, pz, mu_s, var_s);
+    long cnt = 0;
+    for (long i = 0; i < n; ++i)
+        if (var_s[i] > tau && var_m[i] > tau) mu_m[cnt++] = sqrt(var_m[i] / var_s[i]); /* mu_m reused as the list */
+    double med = 1.0;
+    if (cnt > 0) {
+        qsort(mu_m, (size_t)cnt, sizeof(double), cmp_double);
+        med = (cnt % 2) ? mu_m[cnt / 2] : 0.5 * (mu_m[cnt / 2 - 1] + mu_m[cnt / 2]);
+    }
+    free(buf);
+    return med;
+}
+
 int orc_gauss_taps(double sigma, double* w)
 {
     if (!(sigma > 0.0)) return -1;
@@ -369,7 +490,18 @@ void orc_iterate(const double* ct, const double* s, const double* mu_s,
     orc_warp(ct, r, nx, ny, nz, m);
     /* A1 step 1: patch moments (Eq. 3) and a, b (Eq. 5, 6); step 3: I'_s */
     orc_patch_moments(m, nx, ny, nz, p->patch[0], p->patch[1], p->patch[2], mu_m, var_m);
-    orc_correct(mu_m, var_m, mu_s, var_s, s, n, p->var_floor, NULL, NULL, f);
+    if (p->mask_mode == 1) {
+        /* Eq. 7-10 (hu0, a range and h already resolved to absolute values) */
+        double* A = (double*)malloc(sizeof(double) * n);
+        double* B = (double*)malloc(sizeof(double) * n);
+        orc_mask_fill(m, s, mu_m, var_m, mu_s, var_s, nx, ny, nz, p->var_floor, p->hu0, p->a_lo, p->a_hi,
+                      p->fill_h, p->fill_t, p->fill_passes, A, B, NULL);
+        for (long i = 0; i < n; ++i) f[i] = A[i] * s[i] + B[i];
+        free(A);
+        free(B);
+    } else {
+        orc_correct(mu_m, var_m, mu_s, var_s, s, n, p->var_floor, NULL, NULL, f);
+    }
     /* A1 step 4: Eq. 1 force on I'_s; step 5: add dr = -u to r */
     if (p->force_mode == 1)
         orc_force_double(m, f, nx, ny, nz, p->diff_floor, u);
@@ -432,10 +564,25 @@ int orc_register_ex(const double* ct, const double* cbct0, int nx, int ny, int n
     cts[L - 1] = (double*)malloc(sizeof(double) * n);
     ss[L - 1] = (double*)malloc(sizeof(double) * n);
     memcpy(cts[L - 1], ct, sizeof(double) * n);
+    double dhu = orc_mean(ct, n) - orc_mean(cbct0, n);
     if (p->global_shift)
         orc_global_shift(ct, cbct0, n, ss[L - 1]);
     else
         memcpy(ss[L - 1], cbct0, sizeof(double) * n);
+
+    /* Sec. 2.3 parameter rules for the Eq. 7-10 mask, resolved once on the
+     * initial finest-level images: HU_0 = 2 Delta HU, [a_lo, a_hi] a_m with
+     * a_m the median of A, and h (Eq. 10, not given) = HU_0 (1 HU if HU_0 is 0) */
+    orc_params q = *p;
+    if (p->mask_mode == 1) {
+        double am = orc_a_median(ct, ss[L - 1], nx, ny, nz, p->patch[0], p->patch[1], p->patch[2],
+                                 p->var_floor);
+        q.hu0 = p->hu0 > 0.0 ? p->hu0 : 2.0 * fabs(dhu);
+        q.a_lo = p->a_lo * am;
+        q.a_hi = p->a_hi * am;
+        q.fill_h = p->fill_h > 0.0 ? p->fill_h : (q.hu0 > 0.0 ? q.hu0 : 1.0);
+    }
+    p = &q;
 
     /* A1: down-sample to the coarsest resolution */
     for (int l = L - 2; l >= 0; --l) {

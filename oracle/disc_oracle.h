@@ -40,6 +40,12 @@ typedef struct {
     int    force_mode;   /* 0: Eq. 1 static-gradient term; 1: both terms of Eq. 1 */
     double stop_eps;     /* > 0: Sec. 2.3 stopping rule with this epsilon; iters[] caps */
     int    stop_lag;     /* the rule compares l^(k - lag) with l^(k) (10 in Sec. 2.3) */
+    int    mask_mode;    /* 1: Eq. 7-10 mask and weighted fill of a, b (Sec. 2.2-2.3) */
+    double hu0;          /* HU_0 of Eq. 7; <= 0: 2 |Delta HU| (Sec. 2.3) */
+    double a_lo, a_hi;   /* a range as multiples of the median a_m (0.5, 1.5; Sec. 2.3) */
+    double fill_h;       /* h of Eq. 10; <= 0: the HU_0 in use */
+    int    fill_t[3];    /* region T of Eq. 8-9 (7, 7, 3) */
+    int    fill_passes;  /* at most this many fill passes per iteration */
 } orc_params;
 
 /* Number of OpenMP threads the whole-volume functions use. */
@@ -96,6 +102,34 @@ int orc_gauss_taps(double sigma, double* w);
 /* Algorithm A1 step 6: separable Gaussian of one scalar volume (x, y, z
  * passes), indices clamped. */
 void orc_gauss(const double* in, int nx, int ny, int nz, double sigma, double* out);
+
+/* Sec. 2.2 Eq. 7-10 on one level: with (a, b) of Eq. 5-6 per voxel (flat
+ * static patch: a = 1), the mask xi = 1 where |m - s| > hu0 or a outside
+ * [a_min, a_max]; masked voxels get a, b := 0 and are then filled, pass by
+ * pass, with the Eq. 8-9 average over the voxels of the T region (inside
+ * the volume) that are unmasked or were filled by an earlier pass, weights
+ * exp(-(s_i - s_x)^2 / h^2) (Eq. 10). A voxel with no such neighbour (or a
+ * zero weight sum) waits for the next pass. Passes stop when every voxel is
+ * filled or after `passes`; a voxel still unfilled then keeps its Eq. 5-6
+ * values. Writes A, B (N each), xi (N, may be NULL) and returns the number
+ * of passes that filled at least one voxel. */
+int orc_mask_fill(const double* m, const double* s, const double* mu_m, const double* var_m,
+                  const double* mu_s, const double* var_s, int nx, int ny, int nz, double tau,
+                  double hu0, double a_min, double a_max, double h, const int t[3], int passes,
+                  double* A, double* B, unsigned char* xi);
+
+/* The fill alone (Eq. 8-10) from given (a, b) and initial validity
+ * valid0[x] (1 = unmasked): same passes and leftover rule as above. */
+int orc_fill(const double* a0, const double* b0, const unsigned char* valid0, const double* s,
+             int nx, int ny, int nz, double h, const int t[3], int passes, double* A, double* B);
+
+/* a_m of Sec. 2.3: the median of a = STD(M)/STD(S) (Eq. 5) over the voxels
+ * where neither patch is flat (var > tau: a flat CT patch gives a = 0, which
+ * carries no contrast ratio), computed once on the initial images (m = CT,
+ * finest level); an even count averages the two middle values; 1 if no
+ * voxel qualifies. */
+double orc_a_median(const double* ct, const double* s, int nx, int ny, int nz, int px, int py, int pz,
+                    double tau);
 
 /* One DISC iteration at one level (Algorithm A1 steps 1, 3-6):
  * m = warp(ct, r); moments of m; f = a s + b; u = force; r = G * (r - u).

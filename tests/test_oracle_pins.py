@@ -551,3 +551,97 @@ def test_stopping_rule():
     assert n_id == [lag + 1] and np.all(h_id[0] == 0.0)
     _, _, n_off, _ = oracle.register_ex(ct, cb, oracle.make_params(patch=(3, 3, 3), iters=(K,), stop_eps=0.0))
     assert n_off == [K]
+
+
+# --------------------------------------------------------------------------
+# Eq. 7-10: mask and weighted fill of a, b
+# --------------------------------------------------------------------------
+
+def test_fill_weighted_average_hand_worked():
+    """A 3-voxel line, middle voxel masked: Eq. 8-10 by hand,
+    a = (w0 a0 + w2 a2) / (w0 + w2) with w = exp(-(s_i - s_x)^2 / h^2)."""
+    s = np.array([0.0, 10.0, 30.0]).reshape(1, 1, 3)
+    a0 = np.array([1.0, 9.0, 3.0]).reshape(s.shape)
+    b0 = np.array([-5.0, 9.0, 7.0]).reshape(s.shape)
+    valid = np.array([1, 0, 1], bool).reshape(s.shape)
+    A, B, used = oracle.fill(a0, b0, valid, s, h=20.0, t=(3, 1, 1), passes=4)
+    w0, w2 = np.exp(-100.0 / 400.0), np.exp(-400.0 / 400.0)
+    assert used == 1
+    assert abs(A[0, 0, 1] - (w0 * 1.0 + w2 * 3.0) / (w0 + w2)) < 1e-15
+    assert abs(B[0, 0, 1] - (w0 * -5.0 + w2 * 7.0) / (w0 + w2)) < 1e-14
+    assert A[0, 0, 0] == 1.0 and A[0, 0, 2] == 3.0  # unmasked voxels unchanged
+
+
+def test_fill_passes_jacobi_reach_and_leftover():
+    """A line valid only at x = 0, T of radius 1: pass p fills x = p (a voxel
+    filled in a pass is not used in that same pass), every filled value is
+    a0[0], and voxels beyond the last pass keep their Eq. 5-6 values."""
+    n = 8
+    s = np.zeros((1, 1, n))
+    a0 = np.arange(n, dtype=float).reshape(s.shape) + 2.0
+    b0 = -a0
+    valid = np.zeros(s.shape, bool)
+    valid[0, 0, 0] = True
+    A, B, used = oracle.fill(a0, b0, valid, s, h=50.0, t=(3, 1, 1), passes=3)
+    assert used == 3
+    assert np.array_equal(A[0, 0, :4], [2.0] * 4) and np.array_equal(B[0, 0, :4], [-2.0] * 4)
+    assert np.array_equal(A[0, 0, 4:], a0[0, 0, 4:]) and np.array_equal(B[0, 0, 4:], b0[0, 0, 4:])
+    A, _, used = oracle.fill(a0, b0, valid, s, h=50.0, t=(3, 1, 1), passes=20)
+    assert used == n - 1 and np.all(A == 2.0)
+
+
+def test_fill_region_stays_inside_the_volume():
+    """T counts only voxels inside the volume (no edge replication): with
+    uniform s, x = 1 masked and radius 2 along x, the fill is the plain mean
+    over x = 0, 2, 3; a replicated edge would count x = 0 twice."""
+    s = np.zeros((1, 1, 5))
+    a0 = np.array([1.0, 0.0, 4.0, 7.0, 100.0]).reshape(s.shape)
+    valid = np.array([1, 0, 1, 1, 1], bool).reshape(s.shape)
+    A, _, _ = oracle.fill(a0, a0, valid, s, h=10.0, t=(5, 1, 1), passes=1)
+    assert abs(A[0, 0, 1] - (1.0 + 4.0 + 7.0) / 3.0) < 1e-15
+
+
+def test_mask_and_median_against_library_moments():
+    """xi = |m - s| > HU0 or a outside [a_min, a_max] (Eq. 7), with a from
+    scipy box moments; a_m = numpy median over voxels where neither patch is
+    flat; the unmasked voxels keep Eq. 5-6 values."""
+    g = rng(9)
+    shape = (6, 9, 11)
+    m = g.normal(0.0, 100.0, shape).cumsum(axis=2)
+    s = 0.9 * m + g.normal(0.0, 40.0, shape)
+    size = (3, 3, 3)
+
+    def mom(v):
+        mu = ndi.uniform_filter(v, size=size, mode="nearest")
+        return mu, np.maximum(ndi.uniform_filter(v * v, size=size, mode="nearest") - mu * mu, 0.0)
+
+    mu_m, var_m = mom(m)
+    mu_s, var_s = mom(s)
+    a = np.where(var_s > 1e-2, np.sqrt(var_m / var_s), 1.0)
+    b = mu_m - a * mu_s
+    both = (var_s > 1e-2) & (var_m > 1e-2)
+    am = oracle.a_median(m, s, (3, 3, 3))
+    assert abs(am - np.median(np.sqrt(var_m[both] / var_s[both]))) < 1e-9
+    hu0, lo, hi = 60.0, 0.5 * am, 1.5 * am
+    A, B, xi, _ = oracle.mask_fill(m, s, (3, 3, 3), 1e-2, hu0, lo, hi, h=hu0, passes=10)
+    ref = (np.abs(m - s) > hu0) | (a < lo) | (a > hi)
+    near = (np.abs(np.abs(m - s) - hu0) < 1e-6) | (np.abs(a - lo) < 1e-9) | (np.abs(a - hi) < 1e-9)
+    assert np.array_equal(xi[~near], ref[~near]) and 0.05 < xi.mean() < 0.95
+    keep = ~xi
+    assert np.allclose(A[keep], a[keep], rtol=1e-9) and np.allclose(B[keep], b[keep], rtol=1e-9, atol=1e-6)
+
+
+def test_mask_off_limits_and_identical_images():
+    """A mask that never fires (huge HU0, a range [0, inf)) gives the hot
+    path bitwise; identical images stay an exact fixed point with the mask
+    on (a = 1 everywhere, nothing masked)."""
+    from synth.phantom import make_case
+
+    c = make_case("c1")
+    ct, cb = c.ct.astype(np.float64), c.cbct.astype(np.float64)
+    base = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(4,))
+    r0, f0 = oracle.register(ct, cb, oracle.make_params(**base))
+    r1, f1 = oracle.register(ct, cb, oracle.make_params(mask_mode=1, hu0=1e9, a_lo=0.0, a_hi=1e300, **base))
+    assert np.array_equal(r0, r1) and np.array_equal(f0, f1)
+    r2, f2 = oracle.register(ct, ct.copy(), oracle.make_params(mask_mode=1, **base))
+    assert np.abs(r2).max() == 0.0
