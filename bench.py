@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -42,6 +44,100 @@ WORKLOADS = {
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def _ms_per_call(fn, reps, warm=2):
+    import torch
+
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / reps
+
+
+def finest_level_rate(reg, ct, cb, cfg, reps=3):
+    """Wall time of the finest level's iterations alone (the coarse levels
+    and the set-up run first, untimed); median of reps runs."""
+    import torch
+
+    times = []
+    for _ in range(reps):
+        reg.set_volumes(ct, cb)
+        if cfg["levels"] > 1:
+            reg.iterate(sum(cfg["iters"][:-1]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reg.iterate(cfg["iters"][-1])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = sorted(times)[len(times) // 2]
+    n = float(cfg["shape"][0] * cfg["shape"][1] * cfg["shape"][2])
+    return {"ms": round(t * 1000.0, 3), "iterations": cfg["iters"][-1],
+            "voxel_iterations_per_s": round(n * cfg["iters"][-1] / t, 1),
+            "ms_per_iteration": round(t * 1000.0 / cfg["iters"][-1], 4)}
+
+
+def backward_rate(disc, ct, cb, r, cfg, plain_ms_per_it, reps=10):
+    """Differentiable DISC at the workload size: SSD loss alone and loss +
+    hand-written gradient (patch moments recomputed), against one plain
+    finest-level iteration on the same GPU."""
+    patch = cfg["patch"]
+    ys = disc.static_stats(cb, patch)
+    ms_loss = _ms_per_call(lambda: disc.ssd_loss(ct, ys, r, patch), reps)
+    ms_grad = _ms_per_call(lambda: disc.ssd_grad(ct, ys, r, patch, want_loss=True), reps)
+    n = float(ct.numel())
+    return {"ms_loss": round(ms_loss, 4), "ms_loss_and_grad": round(ms_grad, 4),
+            "voxels_per_s_loss_and_grad": round(n / (ms_grad * 1e-3), 1),
+            "vs_plain_iteration": round(ms_grad / plain_ms_per_it, 3)}
+
+
+def batched_rate(disc, n_pairs=16, iters=100):
+    """Batched DISC: n uneven head-and-neck pairs (sizes drawn from
+    128^2x64, 192^2x80, 256^2x96, 384^2x128), patch 11^3, sigma 2, one level,
+    `iters` iterations: sequential single-volume registrations against one
+    batch (eager launches, and the captured graph), tiles autotuned."""
+    import torch
+
+    from synth.phantom import make_batch
+
+    cases = make_batch(n_pairs, device="cuda")
+    cts = [torch.from_numpy(c.ct).cuda() for c in cases]
+    cbs = [torch.from_numpy(c.cbct).cuda() for c in cases]
+    shapes = [tuple(c.ct.shape) for c in cases]
+    vox = float(sum(int(np.prod(s)) for s in shapes))
+    kw = dict(patch=(11, 11, 11), sigma=2.0)
+    regs = [disc.Registration(levels=1, iters=(iters,), **kw) for _ in cases]
+
+    def seq():
+        for reg, ct, cb in zip(regs, cts, cbs):
+            reg.set_volumes(ct, cb)
+            reg.run()
+
+    ms_seq = _ms_per_call(seq, reps=1, warm=1)
+    b = disc.Batch(shapes, iters=iters, **kw)
+    tiles, ms_tune, _ = disc.autotune(b, cts, cbs, cache_path=None, iters=3)
+
+    def run(graph):
+        def f():
+            b.set_volumes(cts, cbs)
+            b.run(use_graph=graph)
+        return f
+
+    ms_eager = _ms_per_call(run(False), reps=1, warm=1)
+    ms_graph = _ms_per_call(run(True), reps=2, warm=1)
+    # batched result against the single-volume path, first pair
+    fe = (b.field(0) - regs[0].field()).abs().max().item()
+    return {"pairs": n_pairs, "shapes_zyx": [list(s) for s in shapes], "voxels": vox, "iterations": iters,
+            "ms_sequential": round(ms_seq, 3), "ms_batched_eager": round(ms_eager, 3),
+            "ms_batched_graph": round(ms_graph, 3),
+            "voxel_iterations_per_s_graph": round(vox * iters / (ms_graph * 1e-3), 1),
+            "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 3),
+            "tiles": tiles, "autotune_ms_per_iteration": round(ms_tune, 4),
+            "pair0_field_max_diff_vs_single": fe}
 
 
 def cpu_baseline(case, params, budget_s=20.0, max_iters=10):
@@ -86,6 +182,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="hn256x256x96", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the finest-level, differentiable and batched measurements")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events in the timed steps")
     ap.add_argument("--dump-inputs", metavar="DIR",
                     help="write the workload's CT and CBCT as raw float32 files (for the native driver) and exit")
@@ -211,6 +309,22 @@ def main():
     }
     if roofline is not None:
         out["roofline"] = roofline
+    if not args.no_extras:
+        fin = finest_level_rate(reg, ct, cb, cfg)
+        log("finest level alone: %.3f ms for %d iterations, %.3g voxel-it/s" % (
+            fin["ms"], fin["iterations"], fin["voxel_iterations_per_s"]))
+        out["finest_level"] = fin
+        r_mid = torch.from_numpy(0.6 * case.r_true).float().contiguous().to(dev)
+        bwd = backward_rate(disc, ct, cb, r_mid, cfg, fin["ms_per_iteration"])
+        log("differentiable: loss %.3f ms, loss + gradient %.3f ms (%.2fx a plain iteration)" % (
+            bwd["ms_loss"], bwd["ms_loss_and_grad"], bwd["vs_plain_iteration"]))
+        out["backward"] = bwd
+        log("batched: generating 16 uneven pairs")
+        bat = batched_rate(disc)
+        log("batched: sequential %.1f ms, batch eager %.1f ms, batch graph %.1f ms (%.2fx), tiles %s" % (
+            bat["ms_sequential"], bat["ms_batched_eager"], bat["ms_batched_graph"],
+            bat["speedup_graph_vs_sequential"], bat["tiles"]))
+        out["batched"] = bat
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(case, params)

@@ -42,6 +42,7 @@ extern "C" {
 #endif
 
 #define DISC_MAX_LEVELS 8
+#define DISC_MAX_BATCH 16
 
 typedef struct disc_ctx disc_ctx;
 
@@ -63,10 +64,26 @@ typedef struct {
     float var_floor;     /* tau (HU^2): a static patch with variance <= tau is flat and
                             only its mean is matched (a = 1) */
     float diff_floor;    /* eps_d (HU): |m - I'_s| < eps_d gives a zero force */
+    int   force_mode;    /* 0: Eq. 1 static-gradient term on I'_s; 1: both terms of Eq. 1
+                            (double force: adds d grad m / (|grad m|^2 + d^2)) */
+    float stop_eps;      /* 0: fixed iteration counts. > 0: Sec. 2.3 stopping rule with
+                            epsilon stop_eps; iters[] then caps each level */
+    int   stop_lag;      /* the rule compares l^(k - stop_lag) with l^(k) (10 in Sec. 2.3) */
+    int   mask_mode;     /* 0: Eq. 5-6 everywhere. 1: Eq. 7 mask and Eq. 8-10 fill of a, b */
+    float hu0;           /* HU_0 of Eq. 7 (HU); <= 0: 2 |mean(CT) - mean(CBCT)| (Sec. 2.3) */
+    float a_lo, a_hi;    /* a range [a_lo a_m, a_hi a_m], a_m the median of Eq. 5 on the
+                            initial images over voxels where neither patch is flat (0.5, 1.5) */
+    float fill_h;        /* h of Eq. 10 (HU); <= 0: the HU_0 in use (1 HU if that is 0) */
+    int   fill_t[3];     /* region T of Eq. 8-9, odd extents (7, 7, 3), counted inside the volume */
+    int   fill_passes;   /* fill passes per iteration, 1..64 (10); a voxel still unfilled keeps
+                            its Eq. 5-6 a, b */
 } disc_params;
 
 /* Defaults: patch 11^3, sigma 2, 3 levels x 100 iterations, global shift on,
- * tau = 1e-2 HU^2, eps_d = 1e-3 HU. */
+ * tau = 1e-2 HU^2, eps_d = 1e-3 HU, static-gradient force, fixed counts
+ * (stop_eps = 0, stop_lag = 10), no mask (mask_mode 0; its settings default
+ * to the Sec. 2.3 rules: hu0 0 = 2 Delta HU, a range 0.5..1.5 a_m, h = HU_0,
+ * T = 7x7x3, 10 passes). */
 int disc_params_default(disc_params* p);
 
 /* Validates *p and creates a host-side context. Does not touch the GPU.
@@ -98,7 +115,14 @@ int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev,
  * moments, correction, force, update, Gaussian. When the current level has
  * done its iters[] count and a finer level exists, the field is first
  * up-sampled (Algorithm A1, last step) and the next level starts. After the
- * finest level's count, further iterations stay at the finest level. */
+ * finest level's count, further iterations stay at the finest level.
+ * With stop_eps > 0 each iteration also evaluates the Sec. 2.3 rule on the
+ * device, without host synchronisation: after iteration k of a level,
+ * l^(k) = sum_x |r^(k+1)(x) - r^(k)(x)| / sum_x |r^(k)(x)| (Euclidean norm per
+ * voxel; 0 if both sums are 0, +inf if only the denominator is), and once
+ * k >= stop_lag and l^(k - stop_lag) - l^(k) <= stop_eps the level is done:
+ * its remaining scheduled iterations become no-ops. disc_state keeps
+ * counting scheduled iterations; disc_get_stats reports the ones run. */
 int disc_iterate(disc_ctx* c, int n, void* stream);
 
 /* Enqueues every iteration left in the schedule. */
@@ -120,6 +144,17 @@ int disc_set_field(disc_ctx* c, const float* r_dev, void* stream);
  * (Sec. 2.2; the corrected CBCT, Sec. 4) to out_dev [nz][ny][nx].
  * DISC_ESTATE before the first iteration of the current level. */
 int disc_get_corrected(disc_ctx* c, float* out_dev, void* stream);
+
+/* Sec. 2.3 stopping rule state of `level` (stop_eps > 0 only, else
+ * DISC_ENOTSUP): *iters_done (may be NULL) = iterations the level ran so far;
+ * l_hist (host, max_k doubles, may be NULL when max_k = 0) receives l^(0),
+ * l^(1), ... (entries past iters_done are 0). Synchronises `stream`. */
+int disc_get_stats(disc_ctx* c, int level, int* iters_done, double* l_hist, int max_k, void* stream);
+
+/* Mask mode: the Sec. 2.3 values resolved at set-up, out = {HU_0, a_min,
+ * a_max, h, a_m} (host array). DISC_ENOTSUP when mask_mode is 0.
+ * Synchronises `stream`. */
+int disc_get_mask_params(disc_ctx* c, float out[5], void* stream);
 
 /* ---- single steps, running the same kernels as disc_iterate ------------ */
 /* All buffers are caller-owned device memory of the stated sizes; inputs
@@ -143,14 +178,15 @@ int disc_step_static_stats(const float* s_dev, int nx, int ny, int nz, const int
 int disc_step_correct(const float* m_dev, const float* ys_dev, int nx, int ny, int nz,
                       const int patch[3], float* f_dev, void* stream);
 
-/* Eq. 1 static-gradient term on f = I'_s, the A1 step-5 update and the
- * step-6 Gaussian: rt = r - (m - f) grad f / (|grad f|^2 + (m - f)^2), zero
- * where |m - f| < diff_floor (central differences, clamped), then
+/* Eq. 1 force on f = I'_s, the A1 step-5 update and the step-6 Gaussian:
+ * rt = r - u with u = (m - f) grad f / (|grad f|^2 + (m - f)^2) (force_mode
+ * 0) or that plus (m - f) grad m / (|grad m|^2 + (m - f)^2) (force_mode 1),
+ * zero where |m - f| < diff_floor (central differences, clamped), then
  * r_out = G_sigma * rt per component. q is 3N floats of scratch (the
  * xy-filtered field); rt (may be NULL) receives r - u. m, f: N floats;
  * r, r_out: 3N floats. */
 int disc_step_force_smooth(const float* m_dev, const float* f_dev, const float* r_dev,
-                           int nx, int ny, int nz, float sigma, float diff_floor,
+                           int nx, int ny, int nz, float sigma, float diff_floor, int force_mode,
                            float* q_dev, float* r_out_dev, float* rt_dev, void* stream);
 
 /* Algorithm A1 step 6 alone: separable Gaussian of each field component,
@@ -176,6 +212,70 @@ int disc_step_downsample(const float* in_dev, int nx, int ny, int nz, float* out
 int disc_step_upsample_field(const float* rc_dev, int cnx, int cny, int cnz,
                              float* rf_dev, int fnx, int fny, int fnz, void* stream);
 
+/* ---- differentiable DISC ------------------------------------------------ */
+/* Loss L(r) = sum_x (m(x) - I'_s(x))^2 between the warped CT m = CT(x + r)
+ * (Sec. 2.1 model) and the static image corrected by patch moment matching
+ * against m (Eq. 3-6; flat static patches match the mean only, a = 1).
+ * ys is the standardised static image from disc_step_static_stats with the
+ * same patch. Gradient (disc_ssd_grad), by the chain rule through Eq. 3-6
+ * and the trilinear warp, recomputing the patch moments of m:
+ *   dL/dm_j = 2 D_j - 2 sum_{x : j in P(x)} D_x (1/n + Y_x (m_j - E_x(M)) / (n STD_x(M)))
+ * with D = m - I'_s, Y = (S - E(S)) / STD(S), P(x) the clamped patch (an
+ * edge voxel counts once per patch offset that clamps onto it), and
+ * dL/dr = dL/dm * d trilinear / d position (one-sided in the cell the warp
+ * samples; 0 along an axis where both corners clamp to the same voxel).
+ * Where STD(M) = 0 the derivative of a is taken as 0.
+ *
+ * ct, ys: N floats; r, grad: 3N floats (field layout); loss_dev: one double,
+ * written by the call (disc_ssd_grad: may be NULL). scale_dev (may be NULL =
+ * 1): one float multiplying the gradient (the upstream dL'/dL of autograd).
+ * scratch_dev: caller-owned device memory, 256-byte aligned, of at least
+ * disc_ssd_scratch_bytes() bytes (about 40 N bytes); contents are not
+ * preserved. Results are deterministic (fixed-order FP64 reductions). */
+size_t disc_ssd_scratch_bytes(int nx, int ny, int nz);
+int disc_ssd_loss(const float* ct_dev, const float* ys_dev, const float* r_dev, int nx, int ny, int nz,
+                  const int patch[3], double* loss_dev, void* scratch_dev, size_t scratch_bytes,
+                  void* stream);
+int disc_ssd_grad(const float* ct_dev, const float* ys_dev, const float* r_dev, int nx, int ny, int nz,
+                  const int patch[3], const float* scale_dev, float* grad_dev, double* loss_dev,
+                  void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* ---- batches of volumes ------------------------------------------------- */
+/* Many independent CT/CBCT pairs of uneven sizes advanced together, one
+ * resolution level, same parameters (Sec. 2.2-2.3 per pair, exactly as
+ * disc_iterate with levels = 1). Each iteration of the whole batch is four
+ * launches (warp; moments + correction; force + xy smoothing; z smoothing),
+ * each covering the workgroups of every volume; with use_graph = 1 the n
+ * iterations are captured once into a HIP graph (on an internal stream) and
+ * replayed on `stream` by later calls with the same n.
+ *
+ * disc_batch_create: p->levels must be 1, p->stop_eps 0 and p->mask_mode 0 (else
+ * DISC_ENOTSUP; force_mode 0 or 1 both run); n in
+ * 1..DISC_MAX_BATCH; dims is [n][3] (nx, ny, nz). Host only.
+ * disc_batch_workspace_bytes: device workspace for all volumes (about 40
+ * bytes per voxel). disc_batch_set_volumes: ct_dev[v], cbct_dev[v] are
+ * device volumes of dims[v] (host arrays of n device pointers); ct is
+ * borrowed until the next set_volumes or destroy; per pair: global shift,
+ * static patch moments, r := 0. disc_batch_set_tiles: launch knobs (moments
+ * tile edge 16 or 32 and workgroup targets per volume of the three sweep
+ * kernels; results may differ in the last bits between knob settings).
+ * disc_batch_iterate: n more iterations of every pair. disc_batch_run: up
+ * to iters[0] in total. disc_batch_get_field / get_corrected: pair v's field
+ * [3][nz][ny][nx] or I'_s of the latest iteration. Errors as elsewhere;
+ * disc_batch_last_error describes the last failure on b. */
+typedef struct disc_batch disc_batch;
+int disc_batch_create(const disc_params* p, int n, const int* dims, disc_batch** out);
+void disc_batch_destroy(disc_batch* b);
+const char* disc_batch_last_error(const disc_batch* b);
+size_t disc_batch_workspace_bytes(const disc_batch* b);
+int disc_batch_set_tiles(disc_batch* b, int mom_ts, int mom_target, int plane_target, int z_target);
+int disc_batch_set_volumes(disc_batch* b, const float* const* ct_dev, const float* const* cbct_dev,
+                           void* workspace_dev, size_t workspace_bytes, void* stream);
+int disc_batch_iterate(disc_batch* b, int n, int use_graph, void* stream);
+int disc_batch_run(disc_batch* b, int use_graph, void* stream);
+int disc_batch_get_field(disc_batch* b, int v, float* out_dev, void* stream);
+int disc_batch_get_corrected(disc_batch* b, int v, float* out_dev, void* stream);
+
 /* ---- measurement helpers ------------------------------------------------ */
 
 /* Plain device copy of `bytes` bytes (16-byte aligned pointers), used to
@@ -186,7 +286,8 @@ int disc_copy_kernel(const void* src_dev, void* dst_dev, size_t bytes, void* str
  * every kernel disc_iterate launches is bracketed by an event pair; the
  * library keeps at most max_records pairs. disc_timing_read synchronises
  * the recorded events and returns, for kernel id k (0 warp, 1 correct,
- * 2 force + xy smoothing, 3 z smoothing, 4 upsample) at pyramid level
+ * 2 force + xy smoothing, 3 z smoothing, 4 upsample, 5 Eq. 8-10 fill passes
+ * and I'_s = a S + b in mask mode) at pyramid level
  * `level` (-1 = all levels), the number of launches, their total
  * milliseconds and the total voxels they processed. Re-enabling (any
  * max_records, 0 = off) clears the records. */

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libdisc.so")
 
 DISC_OK, DISC_EINVAL, DISC_ENOMEM, DISC_EHIP, DISC_ESTATE, DISC_ENOTSUP = 0, -1, -2, -3, -4, -5
 MAX_LEVELS = 8
-KERNELS = {"warp": 0, "correct": 1, "force_xy": 2, "smooth_z": 3, "upsample": 4}
+KERNELS = {"warp": 0, "correct": 1, "force_xy": 2, "smooth_z": 3, "upsample": 4, "fill": 5}
 
 _V = ctypes.c_void_p
 _I = ctypes.c_int
@@ -39,6 +39,16 @@ class Params(ctypes.Structure):
         ("global_shift", ctypes.c_int),
         ("var_floor", ctypes.c_float),
         ("diff_floor", ctypes.c_float),
+        ("force_mode", ctypes.c_int),
+        ("stop_eps", ctypes.c_float),
+        ("stop_lag", ctypes.c_int),
+        ("mask_mode", ctypes.c_int),
+        ("hu0", ctypes.c_float),
+        ("a_lo", ctypes.c_float),
+        ("a_hi", ctypes.c_float),
+        ("fill_h", ctypes.c_float),
+        ("fill_t", ctypes.c_int * 3),
+        ("fill_passes", ctypes.c_int),
     ]
 
 
@@ -67,12 +77,27 @@ _SIGS = [
     ("disc_step_warp", _I, [_V, _V, _I, _I, _I, _V, _V]),
     ("disc_step_static_stats", _I, [_V, _I, _I, _I, _IP, _F, _V, _V]),
     ("disc_step_correct", _I, [_V, _V, _I, _I, _I, _IP, _V, _V]),
-    ("disc_step_force_smooth", _I, [_V, _V, _V, _I, _I, _I, _F, _F, _V, _V, _V, _V]),
+    ("disc_step_force_smooth", _I, [_V, _V, _V, _I, _I, _I, _F, _F, _I, _V, _V, _V, _V]),
+    ("disc_get_stats", _I, [_V, _I, _IP, ctypes.POINTER(ctypes.c_double), _I, _V]),
+    ("disc_get_mask_params", _I, [_V, ctypes.POINTER(ctypes.c_float), _V]),
     ("disc_step_smooth", _I, [_V, _I, _I, _I, _F, _V, _V, _V]),
     ("disc_step_shift_scratch_bytes", ctypes.c_size_t, []),
     ("disc_step_shift", _I, [_V, _V, ctypes.c_long, _V, _V, _V, ctypes.c_size_t, _V]),
     ("disc_step_downsample", _I, [_V, _I, _I, _I, _V, _V]),
     ("disc_step_upsample_field", _I, [_V, _I, _I, _I, _V, _I, _I, _I, _V]),
+    ("disc_ssd_scratch_bytes", ctypes.c_size_t, [_I, _I, _I]),
+    ("disc_ssd_loss", _I, [_V, _V, _V, _I, _I, _I, _IP, _V, _V, ctypes.c_size_t, _V]),
+    ("disc_ssd_grad", _I, [_V, _V, _V, _I, _I, _I, _IP, _V, _V, _V, _V, ctypes.c_size_t, _V]),
+    ("disc_batch_create", _I, [ctypes.POINTER(Params), _I, _IP, ctypes.POINTER(_V)]),
+    ("disc_batch_destroy", None, [_V]),
+    ("disc_batch_last_error", ctypes.c_char_p, [_V]),
+    ("disc_batch_workspace_bytes", ctypes.c_size_t, [_V]),
+    ("disc_batch_set_tiles", _I, [_V, _I, _I, _I, _I]),
+    ("disc_batch_set_volumes", _I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_V), _V, ctypes.c_size_t, _V]),
+    ("disc_batch_iterate", _I, [_V, _I, _I, _V]),
+    ("disc_batch_run", _I, [_V, _I, _V]),
+    ("disc_batch_get_field", _I, [_V, _I, _V, _V]),
+    ("disc_batch_get_corrected", _I, [_V, _I, _V, _V]),
     ("disc_copy_kernel", _I, [_V, _V, ctypes.c_size_t, _V]),
     ("disc_timing_enable", _I, [_V, _I]),
     ("disc_timing_read", _I, [_V, _I, _I, _IP, ctypes.POINTER(ctypes.c_double),
@@ -129,7 +154,8 @@ def _vol_dims(t):
 
 
 def make_params(patch=(11, 11, 11), sigma=2.0, levels=3, iters=(100, 100, 100), global_shift=True,
-                var_floor=1e-2, diff_floor=1e-3):
+                var_floor=1e-2, diff_floor=1e-3, force_mode=0, stop_eps=0.0, stop_lag=10, mask_mode=0,
+                hu0=0.0, a_lo=0.5, a_hi=1.5, fill_h=0.0, fill_t=(7, 7, 3), fill_passes=10):
     p = Params()
     lib().disc_params_default(ctypes.byref(p))
     for d in range(3):
@@ -144,6 +170,17 @@ def make_params(patch=(11, 11, 11), sigma=2.0, levels=3, iters=(100, 100, 100), 
     p.global_shift = 1 if global_shift else 0
     p.var_floor = float(var_floor)
     p.diff_floor = float(diff_floor)
+    p.force_mode = int(force_mode)
+    p.stop_eps = float(stop_eps)
+    p.stop_lag = int(stop_lag)
+    p.mask_mode = int(mask_mode)
+    p.hu0 = float(hu0)
+    p.a_lo = float(a_lo)
+    p.a_hi = float(a_hi)
+    p.fill_h = float(fill_h)
+    for d in range(3):
+        p.fill_t[d] = int(fill_t[d])
+    p.fill_passes = int(fill_passes)
     return p
 
 
@@ -155,8 +192,12 @@ class Registration:
     """
 
     def __init__(self, patch=(11, 11, 11), sigma=2.0, levels=3, iters=(100, 100, 100),
-                 global_shift=True, var_floor=1e-2, diff_floor=1e-3):
-        self.params = make_params(patch, sigma, levels, iters, global_shift, var_floor, diff_floor)
+                 global_shift=True, var_floor=1e-2, diff_floor=1e-3, force_mode=0, stop_eps=0.0,
+                 stop_lag=10, mask_mode=0, hu0=0.0, a_lo=0.5, a_hi=1.5, fill_h=0.0, fill_t=(7, 7, 3),
+                 fill_passes=10):
+        self.params = make_params(patch, sigma, levels, iters, global_shift, var_floor, diff_floor,
+                                  force_mode, stop_eps, stop_lag, mask_mode, hu0, a_lo, a_hi, fill_h, fill_t,
+                                  fill_passes)
         h = _V()
         _check(lib().disc_create(ctypes.byref(self.params), ctypes.byref(h)))
         self._h = h
@@ -220,6 +261,21 @@ class Registration:
         _check(lib().disc_get_corrected(self._h, _dev(out), _stream(stream)), self._h)
         return out
 
+    def stats(self, level, max_k=None, stream=None):
+        """Stopping-rule state of a level: (iterations run, l^(k) for k < that)."""
+        k = int(max_k if max_k is not None else max(self.params.iters[i] for i in range(self.params.levels)))
+        hist = (ctypes.c_double * max(k, 1))()
+        done = ctypes.c_int()
+        _check(lib().disc_get_stats(self._h, int(level), ctypes.byref(done), hist, k, _stream(stream)), self._h)
+        n = int(done.value)
+        return n, [hist[i] for i in range(min(n, k))]
+
+    def mask_params(self, stream=None):
+        """Mask mode: {hu0, a_min, a_max, h, a_m} as resolved at set-up."""
+        out = (ctypes.c_float * 5)()
+        _check(lib().disc_get_mask_params(self._h, out, _stream(stream)), self._h)
+        return dict(zip(("hu0", "a_min", "a_max", "h", "a_m"), [float(v) for v in out]))
+
     def timing_enable(self, max_records):
         _check(lib().disc_timing_enable(self._h, int(max_records)), self._h)
 
@@ -264,15 +320,16 @@ def correct(m, ys, patch, stream=None):
     return f
 
 
-def force_smooth(m, f, r, sigma, diff_floor=1e-3, want_rt=False, stream=None):
-    """Eq. 1 force, update and Gaussian. Returns r_out, or (r_out, r - u)."""
+def force_smooth(m, f, r, sigma, diff_floor=1e-3, want_rt=False, force_mode=0, stream=None):
+    """Eq. 1 force (static-gradient term, or both terms with force_mode=1),
+    update and Gaussian. Returns r_out, or (r_out, r - u)."""
     nx, ny, nz = _vol_dims(m)
     q = torch.empty_like(r)
     out = torch.empty_like(r)
     rt = torch.empty_like(r) if want_rt else None
     _check(lib().disc_step_force_smooth(_dev(m, name="m"), _dev(f, m.shape, "f"),
                                         _dev(r, (3,) + tuple(m.shape), "r"), nx, ny, nz, float(sigma),
-                                        float(diff_floor), _dev(q), _dev(out),
+                                        float(diff_floor), int(force_mode), _dev(q), _dev(out),
                                         _dev(rt) if want_rt else None, _stream(stream)))
     return (out, rt) if want_rt else out
 
@@ -318,3 +375,193 @@ def upsample_field(rc, fine_shape, stream=None):
 def copy_kernel(src, dst, stream=None):
     nbytes = src.numel() * src.element_size()
     _check(lib().disc_copy_kernel(_V(src.data_ptr()), _V(dst.data_ptr()), nbytes, _stream(stream)))
+
+
+# ---- differentiable DISC ---------------------------------------------------
+
+def _ssd_scratch(ct):
+    nx, ny, nz = _vol_dims(ct)
+    nb = int(lib().disc_ssd_scratch_bytes(nx, ny, nz))
+    if nb == 0:
+        raise ValueError("invalid volume dims for the SSD loss")
+    return torch.empty(nb, dtype=torch.uint8, device=ct.device), nb
+
+
+def ssd_loss(ct, ys, r, patch, stream=None):
+    """L = sum (m - I'_s)^2 (float64 0-d device tensor); ys from static_stats."""
+    nx, ny, nz = _vol_dims(ct)
+    scratch, nb = _ssd_scratch(ct)
+    loss = torch.empty((), dtype=torch.float64, device=ct.device)
+    _check(lib().disc_ssd_loss(_dev(ct, name="ct"), _dev(ys, ct.shape, "ys"), _dev(r, (3,) + tuple(ct.shape), "r"),
+                               nx, ny, nz, _patch(patch), _V(loss.data_ptr()), _V(scratch.data_ptr()), nb,
+                               _stream(stream)))
+    return loss
+
+
+def ssd_grad(ct, ys, r, patch, scale=None, want_loss=False, stream=None):
+    """dL/dr (3, nz, ny, nx), times scale (1-element float32 device tensor)."""
+    nx, ny, nz = _vol_dims(ct)
+    scratch, nb = _ssd_scratch(ct)
+    grad = torch.empty_like(r)
+    loss = torch.empty((), dtype=torch.float64, device=ct.device) if want_loss else None
+    if scale is not None and (scale.dtype != torch.float32 or scale.numel() != 1 or not scale.is_cuda):
+        raise TypeError("scale must be a 1-element float32 device tensor")
+    _check(lib().disc_ssd_grad(_dev(ct, name="ct"), _dev(ys, ct.shape, "ys"), _dev(r, (3,) + tuple(ct.shape), "r"),
+                               nx, ny, nz, _patch(patch), _V(scale.data_ptr()) if scale is not None else None,
+                               _dev(grad), _V(loss.data_ptr()) if want_loss else None, _V(scratch.data_ptr()),
+                               nb, _stream(stream)))
+    return (grad, loss) if want_loss else grad
+
+
+class SSDLoss(torch.autograd.Function):
+    """L(r) = sum (m - I'_s)^2 with its hand-written backward (the patch
+    moments are recomputed in the backward pass)."""
+
+    @staticmethod
+    def forward(ctx, r, ct, ys, patch):
+        ctx.save_for_backward(r, ct, ys)
+        ctx.patch = tuple(int(p) for p in patch)
+        return ssd_loss(ct, ys, r, ctx.patch)
+
+    @staticmethod
+    def backward(ctx, g):
+        r, ct, ys = ctx.saved_tensors
+        scale = g.detach().to(torch.float32).reshape(1).contiguous()
+        return ssd_grad(ct, ys, r, ctx.patch, scale=scale), None, None, None
+
+
+def ssd(r, ct, ys, patch):
+    """Differentiable SSD loss of the field r (see SSDLoss)."""
+    return SSDLoss.apply(r, ct, ys, patch)
+
+
+# ---- batches of volumes ------------------------------------------------------
+
+MAX_BATCH = 16
+
+
+class Batch:
+    """Independent CT/CBCT pairs of uneven sizes advanced together (one
+    resolution level): four batched launches per iteration, optionally
+    replayed from a captured HIP graph."""
+
+    def __init__(self, shapes, patch=(11, 11, 11), sigma=2.0, iters=100, global_shift=True,
+                 var_floor=1e-2, diff_floor=1e-3):
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.params = make_params(patch=patch, sigma=sigma, levels=1, iters=(iters,), global_shift=global_shift,
+                                  var_floor=var_floor, diff_floor=diff_floor)
+        n = len(self.shapes)
+        dims = (ctypes.c_int * (3 * n))(*[d for (nz, ny, nx) in self.shapes for d in (nx, ny, nz)])
+        h = _V()
+        _check(lib().disc_batch_create(ctypes.byref(self.params), n, dims, ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+        self._inputs = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().disc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != DISC_OK:
+            m = lib().disc_batch_last_error(self._h)
+            raise DiscError(rc, m.decode() if m else "")
+
+    def set_tiles(self, mom_ts=32, mom_target=256, plane_target=512, z_target=2048):
+        self._check(lib().disc_batch_set_tiles(self._h, int(mom_ts), int(mom_target), int(plane_target),
+                                               int(z_target)))
+
+    def set_volumes(self, cts, cbcts, stream=None):
+        if len(cts) != len(self.shapes) or len(cbcts) != len(self.shapes):
+            raise ValueError("one ct and one cbct per pair")
+        for ct, cb, shp in zip(cts, cbcts, self.shapes):
+            _dev(ct, shp, "ct")
+            _dev(cb, shp, "cbct")
+        nb = int(lib().disc_batch_workspace_bytes(self._h))
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device=cts[0].device)
+        n = len(self.shapes)
+        pc = (_V * n)(*[t.data_ptr() for t in cts])
+        pb = (_V * n)(*[t.data_ptr() for t in cbcts])
+        self._inputs = (cts, cbcts)  # the CTs are borrowed by the library
+        self._check(lib().disc_batch_set_volumes(self._h, pc, pb, _V(self._ws.data_ptr()), nb, _stream(stream)))
+
+    def iterate(self, n=1, use_graph=True, stream=None):
+        self._check(lib().disc_batch_iterate(self._h, int(n), 1 if use_graph else 0, _stream(stream)))
+
+    def run(self, use_graph=True, stream=None):
+        self._check(lib().disc_batch_run(self._h, 1 if use_graph else 0, _stream(stream)))
+
+    def field(self, v, stream=None):
+        out = torch.empty((3,) + self.shapes[v], dtype=torch.float32, device=self._ws.device)
+        self._check(lib().disc_batch_get_field(self._h, int(v), _dev(out), _stream(stream)))
+        return out
+
+    def corrected(self, v, stream=None):
+        out = torch.empty(self.shapes[v], dtype=torch.float32, device=self._ws.device)
+        self._check(lib().disc_batch_get_corrected(self._h, int(v), _dev(out), _stream(stream)))
+        return out
+
+
+# Launch-knob candidates of the batched iteration, tried by the autotuner.
+TILE_CANDIDATES = [
+    dict(mom_ts=32, mom_target=256, plane_target=512, z_target=2048),
+    dict(mom_ts=32, mom_target=128, plane_target=256, z_target=1024),
+    dict(mom_ts=32, mom_target=512, plane_target=1024, z_target=4096),
+    dict(mom_ts=16, mom_target=256, plane_target=512, z_target=2048),
+    dict(mom_ts=16, mom_target=1024, plane_target=1024, z_target=4096),
+]
+
+
+def autotune_key(shapes, patch, sigma):
+    sh = ";".join("x".join(str(v) for v in s) for s in sorted(tuple(s) for s in shapes))
+    return "%s|p%s|s%g" % (sh, "x".join(str(int(p)) for p in patch), float(sigma))
+
+
+def autotune(batch, cts, cbcts, cache_path=None, iters=5, candidates=None):
+    """Times each candidate tile setting on this batch (eager launches, after
+    one warm-up iteration) and keeps the fastest; results are cached in a
+    JSON file keyed by the sorted shapes, patch and sigma. Leaves the batch
+    set to the chosen tiles and re-initialised (set_volumes). Returns
+    (tiles, ms per iteration, whether it came from the cache)."""
+    import json
+    import time
+
+    key = autotune_key(batch.shapes, batch.params.patch, batch.params.sigma)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    if key in cache:
+        best = cache[key]
+        batch.set_tiles(**best["tiles"])
+        batch.set_volumes(cts, cbcts)
+        return best["tiles"], best["ms_per_iteration"], True
+    results = []
+    for cand in (candidates or TILE_CANDIDATES):
+        batch.set_tiles(**cand)
+        batch.set_volumes(cts, cbcts)
+        batch.iterate(1, use_graph=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.iterate(iters, use_graph=False)
+        torch.cuda.synchronize()
+        results.append(((time.perf_counter() - t0) * 1000.0 / iters, cand))
+    ms, best = min(results, key=lambda r: r[0])
+    batch.set_tiles(**best)
+    batch.set_volumes(cts, cbcts)
+    if cache_path:
+        cache[key] = {"tiles": best, "ms_per_iteration": ms,
+                      "all": [{"tiles": c, "ms_per_iteration": t} for t, c in results]}
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return best, ms, False

@@ -1,6 +1,7 @@
 // C ABI of libdisc: argument validation, workspace layout, the Algorithm A1
 // level schedule and per-kernel event timing. Kernels live in the other
 // translation units; this file only decides what to launch.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -18,7 +19,7 @@ namespace {
 
 thread_local std::string g_thread_err;
 
-enum KernelId { K_WARP = 0, K_CORRECT = 1, K_FORCE_XY = 2, K_SMOOTH_Z = 3, K_UPSAMPLE = 4, K_COUNT = 5 };
+enum KernelId { K_WARP = 0, K_CORRECT = 1, K_FORCE_XY = 2, K_SMOOTH_Z = 3, K_UPSAMPLE = 4, K_FILL = 5, K_COUNT = 6 };
 
 struct TimingRec {
     int kid;
@@ -40,6 +41,22 @@ struct disc_ctx {
     float* m = nullptr;
     float* f = nullptr;
     void* scratch = nullptr;
+    // Sec. 2.3 stopping rule: workgroup norm sums of the z pass, l^(k) per
+    // level (hist_stride entries each), per level {stop flag, iterations run}
+    double* norms = nullptr;
+    double* hist = nullptr;
+    int* flags = nullptr;
+    int hist_stride = 1;
+    int norm_parts = 0;
+    // Eq. 7-10 (mask_mode 1): STD(S) per level, (a, b) and stamps (finest
+    // size), per-pass counters, {HU_0, a_min, a_max, h, a_m}, Delta HU
+    float* sd[DISC_MAX_LEVELS] = {};
+    float2* ab = nullptr;
+    unsigned char* stamp = nullptr;
+    int* left = nullptr;
+    float* consts = nullptr;
+    double* dhu = nullptr;
+    void* med_scratch = nullptr;
     int cur = 0;
     int level = 0;
     int it = 0;
@@ -109,6 +126,24 @@ int check_params(disc_ctx* c, const disc_params* p)
         return fail(c, DISC_EINVAL, "var_floor must be finite and >= 0");
     if (!(p->diff_floor >= 0.0f) || !std::isfinite(p->diff_floor))
         return fail(c, DISC_EINVAL, "diff_floor must be finite and >= 0");
+    if (p->force_mode != 0 && p->force_mode != 1)
+        return fail(c, DISC_EINVAL, "force_mode must be 0 (static-gradient) or 1 (double force)");
+    if (!(p->stop_eps >= 0.0f) || !std::isfinite(p->stop_eps))
+        return fail(c, DISC_EINVAL, "stop_eps must be finite and >= 0");
+    if (p->stop_eps > 0.0f && (p->stop_lag < 1 || p->stop_lag > 1000))
+        return fail(c, DISC_EINVAL, "stop_lag must be in 1..1000");
+    if (p->mask_mode != 0 && p->mask_mode != 1) return fail(c, DISC_EINVAL, "mask_mode must be 0 or 1");
+    if (p->mask_mode == 1) {
+        if (!std::isfinite(p->hu0) || !std::isfinite(p->fill_h))
+            return fail(c, DISC_EINVAL, "hu0 and fill_h must be finite");
+        if (!(p->a_lo >= 0.0f) || !(p->a_hi > p->a_lo) || !std::isfinite(p->a_hi))
+            return fail(c, DISC_EINVAL, "need 0 <= a_lo < a_hi, finite");
+        for (int d = 0; d < 3; ++d)
+            if (p->fill_t[d] < 1 || p->fill_t[d] > 15 || p->fill_t[d] % 2 == 0)
+                return fail(c, DISC_EINVAL, "fill_t extents must be odd, 1..15");
+        if (p->fill_passes < 1 || p->fill_passes > 64)
+            return fail(c, DISC_EINVAL, "fill_passes must be in 1..64");
+    }
     return DISC_OK;
 }
 
@@ -132,7 +167,7 @@ struct Carver {
     }
 };
 
-size_t carve(disc_ctx* c, char* base, int L, const Dims* dims)
+size_t carve(disc_ctx* c, const disc_params* p, char* base, int L, const Dims* dims)
 {
     Carver cv{base};
     const size_t nf = (size_t)dims[L - 1].n();
@@ -152,12 +187,45 @@ size_t carve(disc_ctx* c, char* base, int L, const Dims* dims)
     float* m = (float*)cv.take(nf * 4);
     float* f = (float*)cv.take(nf * 4);
     void* sc = cv.take(disc::shift_scratch_bytes());
+    int parts = 1, stride = 1;
+    for (int l = 0; l < L; ++l) {
+        parts = std::max(parts, disc::smooth_z_blocks(dims[l]));
+        stride = std::max(stride, p->iters[l]);
+    }
+    double* norms = (double*)cv.take((size_t)parts * 2 * sizeof(double));
+    // history and flags are contiguous: one fill clears both at set-up
+    double* hist = (double*)cv.take((size_t)L * stride * sizeof(double) + (size_t)L * 2 * sizeof(int));
+    if (p->mask_mode == 1) {
+        for (int l = 0; l < L; ++l) {
+            float* sdl = (float*)cv.take((size_t)dims[l].n() * 4);
+            if (c) c->sd[l] = sdl;
+        }
+        float2* ab = (float2*)cv.take(nf * sizeof(float2));
+        unsigned char* stamp = (unsigned char*)cv.take(nf);
+        int* left = (int*)cv.take((size_t)(p->fill_passes + 1) * sizeof(int));
+        float* consts = (float*)cv.take(8 * sizeof(float));
+        double* dhu = (double*)cv.take(sizeof(double));
+        void* med = cv.take(disc::median_scratch_bytes());
+        if (c) {
+            c->ab = ab;
+            c->stamp = stamp;
+            c->left = left;
+            c->consts = consts;
+            c->dhu = dhu;
+            c->med_scratch = med;
+        }
+    }
     if (c) {
         c->r[0] = r0;
         c->r[1] = r1;
         c->m = m;
         c->f = f;
         c->scratch = sc;
+        c->norms = norms;
+        c->hist = hist;
+        c->flags = hist ? reinterpret_cast<int*>(hist + (size_t)L * stride) : nullptr;
+        c->hist_stride = stride;
+        c->norm_parts = parts;
     }
     return (cv.off + 255) & ~(size_t)255;
 }
@@ -201,26 +269,56 @@ int one_iteration(disc_ctx* c, hipStream_t st)
     const double vox = (double)d.n();
     float* r = c->r[c->cur];
     float* q = c->r[1 - c->cur];
+    // with the stopping rule on, every kernel of this level checks the
+    // level's flag and the iteration becomes a no-op once it is set
+    const bool rule = c->p.stop_eps > 0.0f;
+    int* flags = rule ? c->flags + 2 * l : nullptr;
+    // the history holds hist_stride >= iters[l] entries: iterations past the
+    // schedule (finest level) run without evaluating the rule again
+    const bool record = rule && c->it < c->hist_stride;
     {
         Timed tm(c, st, K_WARP, l, vox);
-        e = disc::launch_warp(c->ct[l], r, c->m, d, st);
+        e = disc::launch_warp(c->ct[l], r, c->m, d, st, flags);
     }
     if (e != hipSuccess) return hip_fail(c, e, "warp");
-    {
+    if (c->p.mask_mode == 1) {
+        {
+            Timed tm(c, st, K_CORRECT, l, vox);
+            e = disc::launch_fill(reinterpret_cast<float*>(c->left), c->p.fill_passes + 1, 0.0f, st);
+            if (e == hipSuccess)
+                e = disc::launch_mask_moments(c->m, c->ys[l], c->s[l], c->sd[l], c->ab, c->stamp, c->consts, d,
+                                              c->p.patch, st, flags);
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "correct (mask)");
+        {
+            Timed tm(c, st, K_FILL, l, vox);
+            for (int pass = 1; pass <= c->p.fill_passes && e == hipSuccess; ++pass)
+                e = disc::launch_fill_pass(c->ab, c->stamp, c->s[l], c->consts, c->left, pass, d, c->p.fill_t,
+                                           flags, st);
+            if (e == hipSuccess) e = disc::launch_apply_ab(c->ab, c->s[l], c->f, d, flags, st);
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "fill");
+    } else {
         Timed tm(c, st, K_CORRECT, l, vox);
-        e = disc::launch_correct(c->m, c->ys[l], c->f, d, c->p.patch, st);
+        e = disc::launch_correct(c->m, c->ys[l], c->f, d, c->p.patch, st, flags);
+        if (e != hipSuccess) return hip_fail(c, e, "correct");
     }
-    if (e != hipSuccess) return hip_fail(c, e, "correct");
     {
         Timed tm(c, st, K_FORCE_XY, l, vox);
-        e = disc::launch_force_xy(c->m, c->f, r, q, nullptr, d, c->p.diff_floor, c->taps, st);
+        e = disc::launch_force_xy(c->m, c->f, r, q, nullptr, d, c->p.diff_floor, c->p.force_mode, c->taps,
+                                  flags, st);
     }
     if (e != hipSuccess) return hip_fail(c, e, "force + xy smoothing");
     {
         Timed tm(c, st, K_SMOOTH_Z, l, vox);
-        e = disc::launch_smooth_z(q, r, d, c->taps, st);
+        e = disc::launch_smooth_z(q, r, d, c->taps, flags, record ? c->norms : nullptr, st);
     }
     if (e != hipSuccess) return hip_fail(c, e, "z smoothing");
+    if (record) {
+        e = disc::launch_stop_rule(c->norms, disc::smooth_z_blocks(d), c->hist + (size_t)l * c->hist_stride,
+                                   flags, c->it, c->p.stop_lag, (double)c->p.stop_eps, st);
+        if (e != hipSuccess) return hip_fail(c, e, "stopping rule");
+    }
     c->it += 1;
     c->f_valid = true;
     return DISC_OK;
@@ -249,6 +347,17 @@ int disc_params_default(disc_params* p)
     p->global_shift = 1;
     p->var_floor = 1e-2f;
     p->diff_floor = 1e-3f;
+    p->force_mode = 0;
+    p->stop_eps = 0.0f;
+    p->stop_lag = 10;
+    p->mask_mode = 0;
+    p->hu0 = 0.0f;
+    p->a_lo = 0.5f;
+    p->a_hi = 1.5f;
+    p->fill_h = 0.0f;
+    p->fill_t[0] = p->fill_t[1] = 7;
+    p->fill_t[2] = 3;
+    p->fill_passes = 10;
     return DISC_OK;
 }
 
@@ -283,7 +392,7 @@ size_t disc_workspace_bytes(const disc_params* p, int nx, int ny, int nz)
     if (check_params(nullptr, p) != DISC_OK || !valid_dims(nx, ny, nz)) return 0;
     Dims dims[DISC_MAX_LEVELS];
     level_dims(p->levels, nx, ny, nz, dims);
-    return carve(nullptr, nullptr, p->levels, dims);
+    return carve(nullptr, p, nullptr, p->levels, dims);
 }
 
 int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev, int nx, int ny,
@@ -302,15 +411,21 @@ int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev, in
     hipStream_t st = (hipStream_t)stream;
     c->ready = false;
     level_dims(c->L, nx, ny, nz, c->dims);
-    carve(c, (char*)workspace_dev, c->L, c->dims);
+    carve(c, &c->p, (char*)workspace_dev, c->L, c->dims);
     const int L = c->L;
     const Dims fin = c->dims[L - 1];
     c->ct[L - 1] = ct_dev;
     hipError_t e;
+    const bool mask = c->p.mask_mode == 1;
     if (c->p.global_shift) {
-        e = disc::launch_shift(ct_dev, cbct_dev, fin.n(), c->s[L - 1], nullptr, c->scratch, st);
+        e = disc::launch_shift(ct_dev, cbct_dev, fin.n(), c->s[L - 1], mask ? c->dhu : nullptr, c->scratch, st);
         if (e != hipSuccess) return hip_fail(c, e, "global shift");
     } else {
+        if (mask) {
+            // Delta HU alone (HU_0 = 2 |Delta HU|); the shifted copy is scratch
+            e = disc::launch_shift(ct_dev, cbct_dev, fin.n(), reinterpret_cast<float*>(c->ab), c->dhu, c->scratch, st);
+            if (e != hipSuccess) return hip_fail(c, e, "mean difference");
+        }
         e = hipMemcpyAsync(c->s[L - 1], cbct_dev, (size_t)fin.n() * 4, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(c, e, "copy cbct");
     }
@@ -321,11 +436,26 @@ int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev, in
         if (e != hipSuccess) return hip_fail(c, e, "downsample cbct");
     }
     for (int l = 0; l < L; ++l) {
-        e = disc::launch_static_stats(c->s[l], c->ys[l], c->dims[l], c->p.patch, c->p.var_floor, st);
+        e = disc::launch_static_stats(c->s[l], c->ys[l], c->dims[l], c->p.patch, c->p.var_floor, st,
+                                      mask ? c->sd[l] : nullptr);
         if (e != hipSuccess) return hip_fail(c, e, "static patch moments");
+    }
+    if (mask) {
+        // Sec. 2.3 rules on the initial finest images: a_m, then the Eq. 7
+        // and Eq. 10 constants, all on the device (the a list is scratch in ab)
+        float* avals = reinterpret_cast<float*>(c->ab);
+        e = disc::launch_amed_values(ct_dev, c->ys[L - 1], c->sd[L - 1], avals, fin, c->p.patch, c->p.var_floor, st);
+        if (e == hipSuccess)
+            e = disc::launch_mask_consts(avals, fin.n(), c->dhu, c->p.hu0, c->p.a_lo, c->p.a_hi, c->p.fill_h,
+                                         c->med_scratch, c->consts, st);
+        if (e != hipSuccess) return hip_fail(c, e, "mask parameters");
     }
     e = disc::launch_fill(c->r[0], 3 * c->dims[0].n(), 0.0f, st);
     if (e != hipSuccess) return hip_fail(c, e, "zero field");
+    // l^(k) history and stop flags (all-zero bits: 0.0 and 0)
+    e = disc::launch_fill(reinterpret_cast<float*>(c->hist),
+                          (long)(c->L * c->hist_stride * 2 + c->L * 2), 0.0f, st);
+    if (e != hipSuccess) return hip_fail(c, e, "clear stopping-rule state");
     c->cur = 0;
     c->level = 0;
     c->it = 0;
@@ -450,7 +580,7 @@ int disc_step_correct(const float* m_dev, const float* ys_dev, int nx, int ny, i
 }
 
 int disc_step_force_smooth(const float* m_dev, const float* f_dev, const float* r_dev, int nx,
-                           int ny, int nz, float sigma, float diff_floor, float* q_dev,
+                           int ny, int nz, float sigma, float diff_floor, int force_mode, float* q_dev,
                            float* r_out_dev, float* rt_dev, void* stream)
 {
     if (!m_dev || !f_dev || !r_dev || !q_dev || !r_out_dev)
@@ -461,9 +591,11 @@ int disc_step_force_smooth(const float* m_dev, const float* f_dev, const float* 
     disc::GaussTaps t;
     if (!disc::make_gauss_taps(sigma, &t)) return fail(nullptr, DISC_EINVAL, "invalid sigma");
     const Dims d{nx, ny, nz};
-    hipError_t e = disc::launch_force_xy(m_dev, f_dev, r_dev, q_dev, rt_dev, d, diff_floor, t,
+    if (force_mode != 0 && force_mode != 1) return fail(nullptr, DISC_EINVAL, "force_mode must be 0 or 1");
+    hipError_t e = disc::launch_force_xy(m_dev, f_dev, r_dev, q_dev, rt_dev, d, diff_floor, force_mode, t,
+                                         nullptr,
                                          (hipStream_t)stream);
-    if (e == hipSuccess) e = disc::launch_smooth_z(q_dev, r_out_dev, d, t, (hipStream_t)stream);
+    if (e == hipSuccess) e = disc::launch_smooth_z(q_dev, r_out_dev, d, t, nullptr, nullptr, (hipStream_t)stream);
     return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "force + smoothing");
 }
 
@@ -476,7 +608,7 @@ int disc_step_smooth(const float* rt_dev, int nx, int ny, int nz, float sigma, f
     if (!disc::make_gauss_taps(sigma, &t)) return fail(nullptr, DISC_EINVAL, "invalid sigma");
     const Dims d{nx, ny, nz};
     hipError_t e = disc::launch_smooth_xy(rt_dev, q_dev, d, t, (hipStream_t)stream);
-    if (e == hipSuccess) e = disc::launch_smooth_z(q_dev, r_dev, d, t, (hipStream_t)stream);
+    if (e == hipSuccess) e = disc::launch_smooth_z(q_dev, r_dev, d, t, nullptr, nullptr, (hipStream_t)stream);
     return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "smooth");
 }
 
@@ -514,6 +646,131 @@ int disc_step_upsample_field(const float* rc_dev, int cnx, int cny, int cnz, flo
     hipError_t e = disc::launch_upsample_field(rc_dev, Dims{cnx, cny, cnz}, rf_dev,
                                                Dims{fnx, fny, fnz}, (hipStream_t)stream);
     return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "upsample field");
+}
+
+int disc_get_stats(disc_ctx* c, int level, int* iters_done, double* l_hist, int max_k, void* stream)
+{
+    if (!c) return fail(nullptr, DISC_EINVAL, "context is NULL");
+    if (!c->ready) return fail(c, DISC_ESTATE, "disc_set_volumes has not succeeded");
+    if (!(c->p.stop_eps > 0.0f)) return fail(c, DISC_ENOTSUP, "the stopping rule is off (stop_eps = 0)");
+    if (level < 0 || level >= c->L) return fail(c, DISC_EINVAL, "level %d outside 0..%d", level, c->L - 1);
+    if (max_k < 0 || (max_k > 0 && !l_hist)) return fail(c, DISC_EINVAL, "bad history buffer");
+    hipStream_t st = (hipStream_t)stream;
+    int fl[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(fl, c->flags + 2 * level, sizeof fl, hipMemcpyDeviceToHost, st);
+    const int k = std::min(max_k, c->hist_stride);
+    if (e == hipSuccess && k > 0)
+        e = hipMemcpyAsync(l_hist, c->hist + (size_t)level * c->hist_stride, (size_t)k * sizeof(double),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(c, e, "read stopping-rule state");
+    if (iters_done) *iters_done = fl[1];
+    return DISC_OK;
+}
+
+int disc_get_mask_params(disc_ctx* c, float out[5], void* stream)
+{
+    if (!c || !out) return fail(c, DISC_EINVAL, "null pointer");
+    if (!c->ready) return fail(c, DISC_ESTATE, "disc_set_volumes has not succeeded");
+    if (c->p.mask_mode != 1) return fail(c, DISC_ENOTSUP, "mask_mode is 0");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(out, c->consts, 5 * sizeof(float), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e == hipSuccess ? DISC_OK : hip_fail(c, e, "read mask parameters");
+}
+
+// ---- differentiable DISC: SSD loss and gradient ----------------------------
+
+namespace {
+
+// Scratch of the SSD calls: m, D (N floats each), two N-element double2
+// buffers for the adjoint passes, the per-workgroup loss partials.
+struct SsdScratch {
+    float* m;
+    float* dres;
+    double2* a;
+    double2* b;
+    double* partial;
+    size_t bytes;
+};
+
+SsdScratch ssd_carve(char* base, Dims d)
+{
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t n = (size_t)d.n();
+    SsdScratch s;
+    size_t off = 0;
+    s.m = reinterpret_cast<float*>(base + off);
+    off += up(n * sizeof(float));
+    s.dres = reinterpret_cast<float*>(base + off);
+    off += up(n * sizeof(float));
+    s.a = reinterpret_cast<double2*>(base + off);
+    off += up(n * sizeof(double2));
+    s.b = reinterpret_cast<double2*>(base + off);
+    off += up(n * sizeof(double2));
+    s.partial = reinterpret_cast<double*>(base + off);
+    off += up((size_t)disc::ssd_partial_count(d) * sizeof(double));
+    s.bytes = off;
+    return s;
+}
+
+int ssd_check(const float* ct, const float* ys, const float* r, int nx, int ny, int nz,
+              const int patch[3], void* scratch, size_t scratch_bytes)
+{
+    if (!ct || !ys || !r || !patch || !scratch) return fail(nullptr, DISC_EINVAL, "null pointer");
+    DISC_CHECK_DIMS(nx, ny, nz);
+    if (!valid_patch(patch)) return fail(nullptr, DISC_EINVAL, "invalid patch");
+    if ((reinterpret_cast<uintptr_t>(scratch) & 255) != 0)
+        return fail(nullptr, DISC_EINVAL, "scratch must be 256-byte aligned");
+    const size_t need = ssd_carve(nullptr, Dims{nx, ny, nz}).bytes;
+    if (scratch_bytes < need)
+        return fail(nullptr, DISC_ENOMEM, "scratch of %zu bytes, need %zu", scratch_bytes, need);
+    return DISC_OK;
+}
+
+}  // namespace
+
+size_t disc_ssd_scratch_bytes(int nx, int ny, int nz)
+{
+    if (!valid_dims(nx, ny, nz)) return 0;
+    return ssd_carve(nullptr, Dims{nx, ny, nz}).bytes;
+}
+
+int disc_ssd_loss(const float* ct_dev, const float* ys_dev, const float* r_dev, int nx, int ny, int nz,
+                  const int patch[3], double* loss_dev, void* scratch_dev, size_t scratch_bytes,
+                  void* stream)
+{
+    if (!loss_dev) return fail(nullptr, DISC_EINVAL, "null pointer");
+    int rc = ssd_check(ct_dev, ys_dev, r_dev, nx, ny, nz, patch, scratch_dev, scratch_bytes);
+    if (rc != DISC_OK) return rc;
+    const Dims d{nx, ny, nz};
+    const hipStream_t st = (hipStream_t)stream;
+    const SsdScratch s = ssd_carve(static_cast<char*>(scratch_dev), d);
+    hipError_t e = disc::launch_warp(ct_dev, r_dev, s.m, d, st);
+    if (e == hipSuccess) e = disc::launch_ssd_moments(s.m, ys_dev, s.dres, nullptr, s.partial, d, patch, st);
+    if (e == hipSuccess) e = disc::launch_ssd_finish(s.partial, disc::ssd_partial_count(d), loss_dev, st);
+    return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "ssd loss");
+}
+
+int disc_ssd_grad(const float* ct_dev, const float* ys_dev, const float* r_dev, int nx, int ny, int nz,
+                  const int patch[3], const float* scale_dev, float* grad_dev, double* loss_dev,
+                  void* scratch_dev, size_t scratch_bytes, void* stream)
+{
+    if (!grad_dev) return fail(nullptr, DISC_EINVAL, "null pointer");
+    int rc = ssd_check(ct_dev, ys_dev, r_dev, nx, ny, nz, patch, scratch_dev, scratch_bytes);
+    if (rc != DISC_OK) return rc;
+    const Dims d{nx, ny, nz};
+    const hipStream_t st = (hipStream_t)stream;
+    const SsdScratch s = ssd_carve(static_cast<char*>(scratch_dev), d);
+    hipError_t e = disc::launch_warp(ct_dev, r_dev, s.m, d, st);
+    if (e == hipSuccess) e = disc::launch_ssd_moments(s.m, ys_dev, s.dres, s.a, s.partial, d, patch, st);
+    if (e == hipSuccess) e = disc::launch_box_adjoint(s.a, s.b, d, 0, patch[0] / 2, st);
+    if (e == hipSuccess) e = disc::launch_box_adjoint(s.b, s.a, d, 1, patch[1] / 2, st);
+    if (e == hipSuccess) e = disc::launch_box_adjoint(s.a, s.b, d, 2, patch[2] / 2, st);
+    if (e == hipSuccess) e = disc::launch_ssd_grad(ct_dev, r_dev, s.m, s.dres, s.b, scale_dev, grad_dev, d, st);
+    if (e == hipSuccess && loss_dev)
+        e = disc::launch_ssd_finish(s.partial, disc::ssd_partial_count(d), loss_dev, st);
+    return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "ssd gradient");
 }
 
 int disc_copy_kernel(const void* src_dev, void* dst_dev, size_t bytes, void* stream)
@@ -569,6 +826,267 @@ int disc_timing_read(disc_ctx* c, int kernel_id, int level, int* launches, doubl
     if (total_ms) *total_ms = ms;
     if (total_voxels) *total_voxels = vox;
     return DISC_OK;
+}
+
+// ---- batches of volumes ------------------------------------------------------
+
+}  // extern "C"
+
+struct disc_batch {
+    disc_params p;
+    disc::GaussTaps taps;
+    disc::BatchTiles tiles;
+    int n = 0;
+    std::vector<Dims> dims;
+    std::vector<disc::BatchVol> vols;
+    std::vector<float*> s;
+    void* shift_scratch = nullptr;
+    int it = 0;
+    bool ready = false;
+    bool f_valid = false;
+    std::string err;
+    // captured iteration loop: graph_iters iterations, replayed by disc_batch_iterate
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_iters = 0;
+};
+
+namespace {
+
+int bfail(disc_batch* b, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+
+int bfail(disc_batch* b, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b)
+        b->err = buf;
+    else
+        g_thread_err = buf;
+    return code;
+}
+
+void drop_graph(disc_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_iters = 0;
+}
+
+hipError_t batch_once(disc_batch* b, hipStream_t st)
+{
+    const disc::BatchVol* v = b->vols.data();
+    hipError_t e = disc::launch_warp_batch(v, b->n, st);
+    if (e == hipSuccess) e = disc::launch_correct_batch(v, b->n, b->p.patch, b->tiles, st);
+    if (e == hipSuccess)
+        e = disc::launch_force_xy_batch(v, b->n, b->p.diff_floor, b->p.force_mode, b->taps, b->tiles.plane_target, st);
+    if (e == hipSuccess) e = disc::launch_smooth_z_batch(v, b->n, b->taps, b->tiles.z_target, st);
+    return e;
+}
+
+size_t batch_bytes(const std::vector<Dims>& dims)
+{
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = up(disc::shift_scratch_bytes());
+    for (const Dims& d : dims) off += 10 * up((size_t)d.n() * sizeof(float));  // s ys m f + r q (3 each)
+    return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+int disc_batch_create(const disc_params* p, int n, const int* dims, disc_batch** out)
+{
+    if (!out) return bfail(nullptr, DISC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(nullptr, p);
+    if (rc != DISC_OK) return rc;
+    if (p->levels != 1)
+        return bfail(nullptr, DISC_ENOTSUP, "batches run one resolution level (levels = 1)");
+    if (p->stop_eps > 0.0f)
+        return bfail(nullptr, DISC_ENOTSUP, "batches run fixed iteration counts (stop_eps = 0)");
+    if (p->mask_mode != 0) return bfail(nullptr, DISC_ENOTSUP, "batches run without the Eq. 7-10 mask");
+    if (n < 1 || n > DISC_MAX_BATCH) return bfail(nullptr, DISC_EINVAL, "batch size %d outside 1..%d", n, DISC_MAX_BATCH);
+    if (!dims) return bfail(nullptr, DISC_EINVAL, "dims is NULL");
+    disc_batch* b = new disc_batch();
+    b->p = *p;
+    disc::make_gauss_taps(p->sigma, &b->taps);
+    b->n = n;
+    for (int v = 0; v < n; ++v) {
+        const int nx = dims[3 * v], ny = dims[3 * v + 1], nz = dims[3 * v + 2];
+        if (!valid_dims(nx, ny, nz)) {
+            delete b;
+            return bfail(nullptr, DISC_EINVAL, "volume %d: dims (%d,%d,%d) invalid", v, nx, ny, nz);
+        }
+        b->dims.push_back(Dims{nx, ny, nz});
+    }
+    b->vols.resize(n);
+    b->s.resize(n);
+    b->tiles = disc::BatchTiles{32, 256, 512, 2048};
+    *out = b;
+    return DISC_OK;
+}
+
+void disc_batch_destroy(disc_batch* b)
+{
+    if (!b) return;
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+const char* disc_batch_last_error(const disc_batch* b)
+{
+    return b ? b->err.c_str() : g_thread_err.c_str();
+}
+
+size_t disc_batch_workspace_bytes(const disc_batch* b)
+{
+    return b ? batch_bytes(b->dims) : 0;
+}
+
+int disc_batch_set_tiles(disc_batch* b, int mom_ts, int mom_target, int plane_target, int z_target)
+{
+    if (!b) return bfail(nullptr, DISC_EINVAL, "batch is NULL");
+    if ((mom_ts != 16 && mom_ts != 32) || mom_target < 1 || plane_target < 1 || z_target < 1)
+        return bfail(b, DISC_EINVAL, "tiles: mom_ts 16 or 32, targets >= 1");
+    b->tiles = disc::BatchTiles{mom_ts, mom_target, plane_target, z_target};
+    drop_graph(b);
+    return DISC_OK;
+}
+
+int disc_batch_set_volumes(disc_batch* b, const float* const* ct_dev, const float* const* cbct_dev,
+                           void* workspace_dev, size_t workspace_bytes, void* stream)
+{
+    if (!b) return bfail(nullptr, DISC_EINVAL, "batch is NULL");
+    if (!ct_dev || !cbct_dev || !workspace_dev) return bfail(b, DISC_EINVAL, "null pointer");
+    for (int v = 0; v < b->n; ++v)
+        if (!ct_dev[v] || !cbct_dev[v]) return bfail(b, DISC_EINVAL, "volume %d: null pointer", v);
+    if (((uintptr_t)workspace_dev & 255) != 0) return bfail(b, DISC_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = batch_bytes(b->dims);
+    if (workspace_bytes < need)
+        return bfail(b, DISC_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    b->ready = false;
+    drop_graph(b);
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    char* base = static_cast<char*>(workspace_dev);
+    size_t off = 0;
+    b->shift_scratch = base;
+    off += up(disc::shift_scratch_bytes());
+    for (int v = 0; v < b->n; ++v) {
+        const Dims d = b->dims[v];
+        const size_t sz = up((size_t)d.n() * sizeof(float));
+        disc::BatchVol& bv = b->vols[v];
+        b->s[v] = reinterpret_cast<float*>(base + off);
+        off += sz;
+        float* ys = reinterpret_cast<float*>(base + off);
+        off += sz;
+        bv.m = reinterpret_cast<float*>(base + off);
+        off += sz;
+        bv.f = reinterpret_cast<float*>(base + off);
+        off += sz;
+        bv.r = reinterpret_cast<float*>(base + off);
+        off += 3 * sz;
+        bv.q = reinterpret_cast<float*>(base + off);
+        off += 3 * sz;
+        bv.ct = ct_dev[v];
+        bv.ys = ys;
+        bv.d = d;
+        hipError_t e;
+        if (b->p.global_shift)
+            e = disc::launch_shift(ct_dev[v], cbct_dev[v], d.n(), b->s[v], nullptr, b->shift_scratch, st);
+        else
+            e = hipMemcpyAsync(b->s[v], cbct_dev[v], (size_t)d.n() * 4, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = disc::launch_static_stats(b->s[v], ys, d, b->p.patch, b->p.var_floor, st);
+        if (e == hipSuccess) e = disc::launch_fill(bv.r, 3 * d.n(), 0.0f, st);
+        if (e != hipSuccess)
+            return bfail(b, DISC_EHIP, "set-up of volume %d: %s", v, hipGetErrorString(e));
+    }
+    b->it = 0;
+    b->f_valid = false;
+    b->ready = true;
+    return DISC_OK;
+}
+
+int disc_batch_iterate(disc_batch* b, int n, int use_graph, void* stream)
+{
+    if (!b) return bfail(nullptr, DISC_EINVAL, "batch is NULL");
+    if (!b->ready) return bfail(b, DISC_ESTATE, "disc_batch_set_volumes has not succeeded");
+    if (n < 0) return bfail(b, DISC_EINVAL, "n must be >= 0");
+    if (n == 0) return DISC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (!use_graph) {
+        for (int k = 0; k < n && e == hipSuccess; ++k) e = batch_once(b, st);
+        if (e != hipSuccess) return bfail(b, DISC_EHIP, "batched iteration: %s", hipGetErrorString(e));
+    } else {
+        if (b->graph_iters != n) {
+            drop_graph(b);
+            if (!b->cap) {
+                e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+                if (e != hipSuccess) return bfail(b, DISC_EHIP, "capture stream: %s", hipGetErrorString(e));
+            }
+            e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) return bfail(b, DISC_EHIP, "begin capture: %s", hipGetErrorString(e));
+            hipError_t le = hipSuccess;
+            for (int k = 0; k < n && le == hipSuccess; ++k) le = batch_once(b, b->cap);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(b->cap, &g);
+            if (le != hipSuccess || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return bfail(b, DISC_EHIP, "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
+            }
+            hipGraphExec_t x = nullptr;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return bfail(b, DISC_EHIP, "instantiate: %s", hipGetErrorString(e));
+            }
+            b->graph = g;
+            b->exec = x;
+            b->graph_iters = n;
+        }
+        e = hipGraphLaunch(b->exec, st);
+        if (e != hipSuccess) return bfail(b, DISC_EHIP, "graph launch: %s", hipGetErrorString(e));
+    }
+    b->it += n;
+    b->f_valid = true;
+    return DISC_OK;
+}
+
+int disc_batch_run(disc_batch* b, int use_graph, void* stream)
+{
+    if (!b) return bfail(nullptr, DISC_EINVAL, "batch is NULL");
+    const int left = b->p.iters[0] - b->it;
+    return disc_batch_iterate(b, left > 0 ? left : 0, use_graph, stream);
+}
+
+int disc_batch_get_field(disc_batch* b, int v, float* out_dev, void* stream)
+{
+    if (!b) return bfail(nullptr, DISC_EINVAL, "batch is NULL");
+    if (!b->ready) return bfail(b, DISC_ESTATE, "disc_batch_set_volumes has not succeeded");
+    if (v < 0 || v >= b->n || !out_dev) return bfail(b, DISC_EINVAL, "bad volume index or null output");
+    const hipError_t e = hipMemcpyAsync(out_dev, b->vols[v].r, (size_t)b->dims[v].n() * 12,
+                                        hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? DISC_OK : bfail(b, DISC_EHIP, "copy field: %s", hipGetErrorString(e));
+}
+
+int disc_batch_get_corrected(disc_batch* b, int v, float* out_dev, void* stream)
+{
+    if (!b) return bfail(nullptr, DISC_EINVAL, "batch is NULL");
+    if (!b->ready || !b->f_valid) return bfail(b, DISC_ESTATE, "no iteration has run");
+    if (v < 0 || v >= b->n || !out_dev) return bfail(b, DISC_EINVAL, "bad volume index or null output");
+    const hipError_t e = hipMemcpyAsync(out_dev, b->vols[v].f, (size_t)b->dims[v].n() * 4,
+                                        hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? DISC_OK : bfail(b, DISC_EHIP, "copy corrected: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

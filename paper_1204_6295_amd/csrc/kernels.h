@@ -30,29 +30,77 @@ struct GaussTaps {
 // Returns false when sigma is outside (0, kMaxGaussR / 3].
 bool make_gauss_taps(float sigma, GaussTaps* t);
 
+// Kernels of an iteration take the level's stop flag (may be null): when it
+// is set (the level met its Sec. 2.3 stopping rule) they return at once.
+
 // m = CT(x + r(x)), trilinear, corner indices clamped.
-hipError_t launch_warp(const float* ct, const float* r, float* m, Dims d, hipStream_t s);
+hipError_t launch_warp(const float* ct, const float* r, float* m, Dims d, hipStream_t s,
+                       const int* stop = nullptr);
 
 // Static-image statistics: ys = (s - mu)/sd, or s - mu with the low mantissa
 // bit set where var <= tau.
 hipError_t launch_static_stats(const float* s, float* ys, Dims d, const int patch[3], float tau,
-                               hipStream_t st);
+                               hipStream_t st, float* sd = nullptr);
 
 // Corrected static image f = mu_M + c ys, c = sd_M (or 1 on flat static patches).
 hipError_t launch_correct(const float* m, const float* ys, float* f, Dims d, const int patch[3],
-                          hipStream_t st);
+                          hipStream_t st, const int* stop = nullptr);
 
-// Per z plane: r~ = r - u (u the Eq. 1 static-gradient force on f) on the tile
-// plus the Gaussian halo, then the x and y Gaussian passes: q = G_xy * r~.
-// rt (optional) receives r~.
+// Per z plane: r~ = r - u (u the Eq. 1 force on f: static-gradient term,
+// force_mode 0, or both terms, force_mode 1) on the tile plus the Gaussian
+// halo, then the x and y Gaussian passes: q = G_xy * r~. rt (optional)
+// receives r~.
 hipError_t launch_force_xy(const float* m, const float* f, const float* r, float* q, float* rt,
-                           Dims d, float eps_d, const GaussTaps& t, hipStream_t st);
+                           Dims d, float eps_d, int force_mode, const GaussTaps& t, const int* stop,
+                           hipStream_t st);
 
 // q = G_xy * rt (x and y passes only).
 hipError_t launch_smooth_xy(const float* rt, float* q, Dims d, const GaussTaps& t, hipStream_t st);
 
-// out = G_z * q (z pass).
-hipError_t launch_smooth_z(const float* q, float* out, Dims d, const GaussTaps& t, hipStream_t st);
+// out = G_z * q (z pass). norms (may be null): out holds r^(k) on entry and
+// each workgroup writes (sum |r^(k+1) - r^(k)|, sum |r^(k)|) in FP64 to
+// norms[2 b], norms[2 b + 1], b < smooth_z_blocks(d).
+hipError_t launch_smooth_z(const float* q, float* out, Dims d, const GaussTaps& t, const int* stop,
+                           double* norms, hipStream_t st);
+int smooth_z_blocks(Dims d);
+// Sec. 2.3 stopping rule after iteration k (see k_stop_rule).
+hipError_t launch_stop_rule(const double* norms, int nparts, double* hist, int* flags, int k, int lag,
+                            double eps, hipStream_t st);
+
+// SSD loss and gradient (differentiable DISC).
+// Moments sweep in SSD mode: dres = m - I'_s, bg = (beta, gamma) adjoint
+// weights (bg may be null: loss only), one FP64 sum of dres^2 per workgroup
+// into partial[0 .. ssd_partial_count(d)).
+int ssd_partial_count(Dims d);
+hipError_t launch_ssd_moments(const float* m, const float* ys, float* dres, double2* bg, double* partial,
+                              Dims d, const int patch[3], hipStream_t st);
+// Transpose of the clamped window sum of radius R along one axis (0 x, 1 y, 2 z).
+hipError_t launch_box_adjoint(const double2* in, double2* out, Dims d, int axis, int R, hipStream_t st);
+// grad = scale * (2 dres - 2 (m B(beta) + B(gamma))) * d trilinear / d position.
+hipError_t launch_ssd_grad(const float* ct, const float* r, const float* m, const float* dres,
+                           const double2* bg, const float* scale, float* grad, Dims d, hipStream_t st);
+// loss = sum of n partial sums, fixed order.
+hipError_t launch_ssd_finish(const double* partial, int n, double* loss, hipStream_t st);
+
+// Eq. 7-10 (mask mode). Moments sweep writing ab = (a, b) of Eq. 5-6 and
+// stamp = 255 where Eq. 7 masks the voxel (consts = {HU_0, a_min, a_max, h}
+// on the device); sd is STD(S) from launch_static_stats.
+hipError_t launch_mask_moments(const float* m, const float* ys, const float* s, const float* sd, float2* ab,
+                               unsigned char* stamp, const float* consts, Dims d, const int patch[3],
+                               hipStream_t st, const int* stop);
+// Fill pass `pass` (1-based) of Eq. 8-10 over the T region t[3]; left[pass]
+// accumulates the voxels still masked (left must be zeroed per iteration).
+hipError_t launch_fill_pass(float2* ab, unsigned char* stamp, const float* s, const float* consts, int* left,
+                            int pass, Dims d, const int t[3], const int* stop, hipStream_t st);
+// f = a S + b.
+hipError_t launch_apply_ab(const float2* ab, const float* s, float* f, Dims d, const int* stop, hipStream_t st);
+// Set-up: a = STD(CT)/STD(S) per voxel (-1 where a patch is flat), then the
+// exact median a_m and consts = {HU_0, a_lo a_m, a_hi a_m, h, a_m}.
+hipError_t launch_amed_values(const float* ct, const float* ys, const float* sd, float* a_out, Dims d,
+                              const int patch[3], float tau, hipStream_t st);
+size_t median_scratch_bytes();
+hipError_t launch_mask_consts(const float* a_vals, long n, const double* dhu, float hu0, float lo_frac,
+                              float hi_frac, float h, void* scratch, float* consts, hipStream_t st);
 
 // Global shift: FP64 partial sums, then s = cbct + (mean ct - mean cbct).
 size_t shift_scratch_bytes();
@@ -77,5 +125,53 @@ __device__ inline int clampi(int v, int n)
 {
     return v < 0 ? 0 : (v > n - 1 ? n - 1 : v);
 }
+
+// ---- batches of volumes in one launch --------------------------------------
+// A batched launch covers the workgroups of up to kMaxBatch volumes:
+// volume v owns workgroups [start[v], start[v + 1]) and its own argument
+// block, all passed by value in the kernel arguments.
+constexpr int kMaxBatch = 16;
+
+template <class A>
+struct Batch {
+    int n;
+    int start[kMaxBatch + 1];
+    A v[kMaxBatch];
+};
+
+// Volume of workgroup bid (n <= kMaxBatch, wave-uniform).
+__device__ inline int batch_volume(const int* start, int n, int bid)
+{
+    int v = 0;
+    for (int i = 1; i < n; ++i) v += bid >= start[i] ? 1 : 0;
+    return v;
+}
+
+// Launch knobs of a batched iteration (chosen by the autotuner).
+struct BatchTiles {
+    int mom_ts;        // moments tile edge: 16 or 32
+    int mom_target;    // moments: about this many workgroups per volume
+    int plane_target;  // force + xy smoothing: workgroups per volume
+    int z_target;      // z smoothing: workgroups per volume
+};
+
+// One volume of a batched iteration: its buffers and dims.
+struct BatchVol {
+    const float* ct;
+    const float* ys;
+    float* r;    // field, updated in place (r -> r~ -> smoothed)
+    float* m;
+    float* f;
+    float* q;    // xy-filtered r~
+    Dims d;
+};
+
+// One DISC iteration of every volume of a batch is these four launches.
+hipError_t launch_warp_batch(const BatchVol* vols, int n, hipStream_t st);
+hipError_t launch_correct_batch(const BatchVol* vols, int n, const int patch[3], const BatchTiles& tiles,
+                                hipStream_t st);
+hipError_t launch_force_xy_batch(const BatchVol* vols, int n, float eps_d, int force_mode, const GaussTaps& t,
+                                 int target, hipStream_t st);
+hipError_t launch_smooth_z_batch(const BatchVol* vols, int n, const GaussTaps& t, int target, hipStream_t st);
 
 }  // namespace disc

@@ -57,14 +57,12 @@ __device__ inline float warp_at(const float* __restrict__ ct, int x, int y, int 
 }
 
 // Two rows per thread (y and y + BY) so that each thread has six field loads
-// and sixteen corner gathers in flight.
-__global__ __launch_bounds__(BX * BY) void k_warp(const float* __restrict__ ct,
-                                                 const float* __restrict__ r,
-                                                 float* __restrict__ m, int nx, int ny, int nz)
+// and sixteen corner gathers in flight. (bx, by, z) is the workgroup's tile.
+__device__ inline void warp_body(const float* __restrict__ ct, const float* __restrict__ r,
+                                 float* __restrict__ m, int nx, int ny, int nz, int bx, int by, int z)
 {
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int ya = blockIdx.y * (2 * BY) + threadIdx.y, yb = ya + BY;
-    const int z = blockIdx.z;
+    const int x = bx * BX + threadIdx.x;
+    const int ya = by * (2 * BY) + threadIdx.y, yb = ya + BY;
     if (x >= nx || ya >= ny) return;
     const long N = (long)nx * ny * nz;
     const long ia = ((long)z * ny + ya) * nx + x;
@@ -80,6 +78,33 @@ __global__ __launch_bounds__(BX * BY) void k_warp(const float* __restrict__ ct,
     const float ma = warp_at(ct, x, ya, z, rxa, rya, rza, nx, ny, nz);
     if (has_b) m[ib] = warp_at(ct, x, yb, z, rxb, ryb, rzb, nx, ny, nz);
     m[ia] = ma;
+}
+
+__global__ __launch_bounds__(BX * BY) void k_warp(const float* __restrict__ ct,
+                                                 const float* __restrict__ r,
+                                                 float* __restrict__ m, int nx, int ny, int nz,
+                                                 const int* __restrict__ stop)
+{
+    if (stop && *stop) return;  // the level has met its stopping rule
+    warp_body(ct, r, m, nx, ny, nz, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+struct WarpArgs {
+    const float* ct;
+    const float* r;
+    float* m;
+    int nx, ny, nz;
+    int gx, gy;  // workgroups along x and y (rows in pairs)
+};
+
+// Batched: the workgroups of volume v tile (x, y pairs, z) in that order.
+__global__ __launch_bounds__(BX * BY) void k_warp_batch(Batch<WarpArgs> b)
+{
+    const int v = batch_volume(b.start, b.n, blockIdx.x);
+    const WarpArgs& a = b.v[v];
+    const int lb = blockIdx.x - b.start[v];
+    const int bx = lb % a.gx, rest = lb / a.gx;
+    warp_body(a.ct, a.r, a.m, a.nx, a.ny, a.nz, bx, rest % a.gy, rest / a.gy);
 }
 
 // Sec. 2.3 multi-scale strategy: 2x2x2 block mean, clamped at odd edges.
@@ -237,10 +262,31 @@ bool make_gauss_taps(float sigma, GaussTaps* t)
     return true;
 }
 
-hipError_t launch_warp(const float* ct, const float* r, float* m, Dims d, hipStream_t s)
+hipError_t launch_warp(const float* ct, const float* r, float* m, Dims d, hipStream_t s, const int* stop)
 {
     const dim3 g((d.nx + BX - 1) / BX, (d.ny + 2 * BY - 1) / (2 * BY), d.nz);
-    hipLaunchKernelGGL(k_warp, g, dim3(BX, BY), 0, s, ct, r, m, d.nx, d.ny, d.nz);
+    hipLaunchKernelGGL(k_warp, g, dim3(BX, BY), 0, s, ct, r, m, d.nx, d.ny, d.nz, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_warp_batch(const BatchVol* vols, int n, hipStream_t s)
+{
+    Batch<WarpArgs> b{};
+    b.n = n;
+    b.start[0] = 0;
+    for (int v = 0; v < n; ++v) {
+        WarpArgs& a = b.v[v];
+        a.ct = vols[v].ct;
+        a.r = vols[v].r;
+        a.m = vols[v].m;
+        a.nx = vols[v].d.nx;
+        a.ny = vols[v].d.ny;
+        a.nz = vols[v].d.nz;
+        a.gx = (a.nx + BX - 1) / BX;
+        a.gy = (a.ny + 2 * BY - 1) / (2 * BY);
+        b.start[v + 1] = b.start[v] + a.gx * a.gy * a.nz;
+    }
+    hipLaunchKernelGGL(k_warp_batch, dim3(b.start[n]), dim3(BX, BY), 0, s, b);
     return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ struct PlaneArgs {
     const float* r;    // field r (force mode) or r~ (plain smoothing)
     float* q;          // xy-filtered r~
     float* rt;         // optional copy of r~ (force mode), may be null
+    const int* stop;   // level's stop flag (stopping rule), may be null
     int nx, ny, nz;
     int zchunk;
     int tiles_x, tiles_y, nblocks;
@@ -38,9 +39,14 @@ struct PlaneArgs {
     GaussTaps taps;
 };
 
-template <int R, bool FORCE, int TX, int TY, bool PIPE>
-__global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
+// One workgroup's z chunk of one column tile; bid is its workgroup index
+// within the volume.
+// FM: 0 smoothing only, 1 Eq. 1 static-gradient force, 2 both Eq. 1 terms.
+template <int R, int FM, int TX, int TY, bool PIPE>
+__device__ __forceinline__ void plane_body(const PlaneArgs& a, const int bid)
 {
+    constexpr bool FORCE = FM > 0, DBL = FM == 2;
+    if (a.stop && *a.stop) return;  // the level has met its stopping rule
     constexpr int NT = TX * TY;
     constexpr int K = 2 * R + 1;
     constexpr int W = TX + 2 * R;
@@ -57,8 +63,9 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
     __shared__ __align__(16) float s_in[3][H][PW];
     __shared__ __align__(16) float s_x[3][H][TX];
     __shared__ float s_f[FORCE ? FH * FW : 1];
+    __shared__ float s_mm[DBL ? FH * FW : 1];  // m region for grad m (double force)
 
-    const int lb = xcd_logical_block(blockIdx.x, a.nblocks);
+    const int lb = xcd_logical_block(bid, a.nblocks);
     const int bx = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
     const int by = rest % a.tiles_y;
@@ -114,11 +121,16 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
     // divergent branches), so the compiler can keep them in flight across
     // the barriers of the current plane
     float pf[NF], pr0[NP], pr1[NP], pr2[NP], pm[NP], pzu[NP], pzd[NP];
+    float pmf[DBL ? NF : 1], pmu[DBL ? NP : 1], pmd[DBL ? NP : 1];
     auto fetch = [&](int z) {
         const long zoff = (long)z * plane;
         if (FORCE) {
 #pragma unroll
             for (int q = 0; q < NF; ++q) pf[q] = a.f[zoff + foff[q]];
+        }
+        if (DBL) {
+#pragma unroll
+            for (int q = 0; q < NF; ++q) pmf[q] = a.m[zoff + foff[q]];
         }
         const long zu = (long)clampi(z + 1, a.nz) * plane, zd = (long)clampi(z - 1, a.nz) * plane;
 #pragma unroll
@@ -131,6 +143,10 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
                 pzu[q] = a.f[zu + pofs[q]];
                 pzd[q] = a.f[zd + pofs[q]];
             }
+            if (DBL) {
+                pmu[q] = a.m[zu + pofs[q]];
+                pmd[q] = a.m[zd + pofs[q]];
+            }
         }
     };
 
@@ -138,7 +154,7 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
     for (int z = z0; z < z1; ++z) {
         const long zoff = (long)z * plane;
         if (!PIPE) fetch(z);
-        float v0[NP], v1[NP], v2[NP], mm[NP], fu[NP], fd[NP];
+        float v0[NP], v1[NP], v2[NP], mm[NP], fu[NP], fd[NP], mu_[DBL ? NP : 1], md_[DBL ? NP : 1];
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
             v0[q] = pr0[q];
@@ -147,11 +163,20 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
             mm[q] = pm[q];
             fu[q] = pzu[q];
             fd[q] = pzd[q];
+            if (DBL) {
+                mu_[q] = pmu[q];
+                md_[q] = pmd[q];
+            }
         }
         if (FORCE) {
 #pragma unroll
             for (int q = 0; q < NF; ++q)
                 if (fval[q]) s_f[t + q * NT] = pf[q];
+        }
+        if (DBL) {
+#pragma unroll
+            for (int q = 0; q < NF; ++q)
+                if (fval[q]) s_mm[t + q * NT] = pmf[q];
         }
         __syncthreads();
         if (PIPE) fetch(min(z + 1, z1 - 1));
@@ -174,6 +199,19 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
                     w0 -= sc * gxv;
                     w1 -= sc * gyv;
                     w2 -= sc * gzv;
+                }
+                if (DBL) {
+                    // second term of Eq. 1: the same with the gradient of m
+                    const float hx = (s_mm[fxp_[q]] - s_mm[fxm_[q]]) * 0.5f;
+                    const float hy = (s_mm[fyp_[q]] - s_mm[fym_[q]]) * 0.5f;
+                    const float hz = (mu_[q] - md_[q]) * 0.5f;
+                    const float den2 = hx * hx + hy * hy + hz * hz + d * d;
+                    if (den2 > 0.0f && fabsf(d) >= a.eps_d) {
+                        const float sc2 = d * __builtin_amdgcn_rcpf(den2);
+                        w0 -= sc2 * hx;
+                        w1 -= sc2 * hy;
+                        w2 -= sc2 * hz;
+                    }
                 }
                 if (a.rt && pint[q]) {
                     a.rt[zoff + pofs[q]] = w0;
@@ -231,29 +269,53 @@ __global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
     }
 }
 
+template <int R, int FM, int TX, int TY, bool PIPE>
+__global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
+{
+    plane_body<R, FM, TX, TY, PIPE>(a, blockIdx.x);
+}
+
+template <int R, int FM, int TX, int TY, bool PIPE>
+__global__ __launch_bounds__(TX* TY) void k_plane_xy_batch(Batch<PlaneArgs> b)
+{
+    const int v = batch_volume(b.start, b.n, blockIdx.x);
+    plane_body<R, FM, TX, TY, PIPE>(b.v[v], blockIdx.x - b.start[v]);
+}
+
 struct ZArgs {
     const float* q;
     float* out;
+    const int* stop;  // level's stop flag (stopping rule), may be null
+    double* norms;    // NORM: per workgroup (sum |r_new - r_old|, sum |r_old|)
     int nx, ny, nz;
     int zchunk;
+    int colblocks;  // workgroups across the columns of one z chunk
     long ncols;
     GaussTaps taps;
 };
 
 constexpr int ZNT = 256;
 
-template <int R>
-__global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
+// One workgroup: ZNT columns of one z chunk; bid = chunk * colblocks + column
+// block. NORM: out holds r^(k) on entry; the workgroup also sums, in FP64,
+// the Euclidean norms of r^(k+1) - r^(k) and of r^(k) over its voxels (the
+// two sums of l^(k), Sec. 2.3).
+template <int R, bool NORM>
+__device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
 {
     constexpr int K = 2 * R + 1;
-    const long col = (long)blockIdx.x * ZNT + threadIdx.x;
-    if (col >= a.ncols) return;
-    const int z0 = blockIdx.y * a.zchunk;
+    if (a.stop && *a.stop) return;  // the level has met its stopping rule
+    const long col0 = (long)(bid % a.colblocks) * ZNT + threadIdx.x;
+    if (!NORM && col0 >= a.ncols) return;
+    const bool act = col0 < a.ncols;
+    const long col = act ? col0 : a.ncols - 1;  // idle lanes (NORM) read a valid column
+    const int z0 = (bid / a.colblocks) * a.zchunk;
     const int z1 = min(a.nz, z0 + a.zchunk);
     const long plane = (long)a.nx * a.ny;
     const long N = plane * a.nz;
     float ring[3][K];
     float n1[3], n2[3];  // the next two planes, loads in flight
+    double s_dr = 0.0, s_r = 0.0;
     auto load = [&](int p, float* dst) {
         const long o = (long)clampi(z0 - R + p, a.nz) * plane + col;
         dst[0] = a.q[o];
@@ -267,7 +329,8 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int p = p0 + k;
-            if (p >= nplanes) break;
+            if (NORM ? p >= nplanes : false) continue;  // uniform guard keeps the loop unrollable
+            if (!NORM && p >= nplanes) break;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 ring[c][k] = n1[c];
@@ -276,15 +339,93 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
             load(p + 2, n2);  // past the chunk end this re-reads a clamped plane
             if (p >= K - 1) {
                 const long o = (long)(z0 + p - 2 * R) * plane + col;
+                float nv[3], ov[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     float sacc = 0.0f;
 #pragma unroll
                     for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], ring[c][(k + 1 + j) % K], sacc);
-                    a.out[c * N + o] = sacc;
+                    nv[c] = sacc;
+                    if (NORM) ov[c] = a.out[c * N + o];
+                }
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) a.out[c * N + o] = nv[c];
+                }
+                if (NORM && act) {
+                    const float dx = nv[0] - ov[0], dy = nv[1] - ov[1], dz = nv[2] - ov[2];
+                    s_dr += (double)sqrtf(dx * dx + dy * dy + dz * dz);
+                    s_r += (double)sqrtf(ov[0] * ov[0] + ov[1] * ov[1] + ov[2] * ov[2]);
                 }
             }
         }
+    }
+    if (NORM) {
+        // fixed-order tree over the workgroup
+        __shared__ double red[2][ZNT];
+        const int t = threadIdx.x;
+        red[0][t] = s_dr;
+        red[1][t] = s_r;
+        __syncthreads();
+        for (int h = ZNT / 2; h > 0; h >>= 1) {
+            if (t < h) {
+                red[0][t] += red[0][t + h];
+                red[1][t] += red[1][t + h];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            a.norms[2 * bid] = red[0][0];
+            a.norms[2 * bid + 1] = red[1][0];
+        }
+    }
+}
+
+template <int R, bool NORM>
+__global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
+{
+    smooth_z_body<R, NORM>(a, blockIdx.x);
+}
+
+template <int R>
+__global__ __launch_bounds__(ZNT) void k_smooth_z_batch(Batch<ZArgs> b)
+{
+    const int v = batch_volume(b.start, b.n, blockIdx.x);
+    smooth_z_body<R, false>(b.v[v], blockIdx.x - b.start[v]);
+}
+
+// Sec. 2.3 stopping rule after iteration k of a level: l^(k) = sum |dr| /
+// sum |r| from the workgroup partial sums (fixed order), recorded in hist[k];
+// flags[0] := 1 once k >= lag and hist[k - lag] - l^(k) <= eps; flags[1]
+// counts the iterations run.
+__global__ __launch_bounds__(256) void k_stop_rule(const double* __restrict__ norms, int nparts,
+                                                  double* __restrict__ hist, int* __restrict__ flags,
+                                                  int k, int lag, double eps)
+{
+    if (flags[0]) return;
+    __shared__ double red[2][256];
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0;
+    for (int i = t; i < nparts; i += 256) {
+        a0 += norms[2 * i];
+        a1 += norms[2 * i + 1];
+    }
+    red[0][t] = a0;
+    red[1][t] = a1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            red[0][t] += red[0][t + h];
+            red[1][t] += red[1][t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double num = red[0][0], den = red[1][0];
+        const double l = den > 0.0 ? num / den : (num > 0.0 ? __builtin_huge_val() : 0.0);
+        hist[k] = l;
+        flags[1] = k + 1;
+        if (k >= lag && hist[k - lag] - l <= eps) flags[0] = 1;
     }
 }
 
@@ -293,13 +434,13 @@ constexpr int PTX = 32;
 constexpr int PTY = 32;
 constexpr bool PPIPE = true;
 
-template <bool FORCE>
+template <int FM>
 hipError_t launch_plane(const PlaneArgs& a, int R, hipStream_t st)
 {
     const dim3 g(a.nblocks);
     switch (R) {
 #define DISC_R(RR) \
-    case RR: hipLaunchKernelGGL((k_plane_xy<RR, FORCE, PTX, PTY, PPIPE>), g, dim3(PTX * PTY), 0, st, a); break;
+    case RR: hipLaunchKernelGGL((k_plane_xy<RR, FM, PTX, PTY, PPIPE>), g, dim3(PTX * PTY), 0, st, a); break;
         DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
 #undef DISC_R
         default: return hipErrorInvalidValue;
@@ -307,27 +448,49 @@ hipError_t launch_plane(const PlaneArgs& a, int R, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_z(const float* q, float* out, Dims d, const GaussTaps& t, hipStream_t st)
+// z chunks: about `target` workgroups in the launch; re-read halo planes
+// come from cache.
+ZArgs z_args(const float* q, float* out, Dims d, const GaussTaps& t, int target = 2048)
 {
     ZArgs a;
     a.q = q;
     a.out = out;
+    a.stop = nullptr;
+    a.norms = nullptr;
     a.nx = d.nx;
     a.ny = d.ny;
     a.nz = d.nz;
     a.ncols = (long)d.nx * d.ny;
     a.taps = t;
-    // z chunks: about 4 workgroups per CU; re-read halo planes come from cache
     const long colblocks = (a.ncols + ZNT - 1) / ZNT;
-    int chunks = (int)((2048 + colblocks - 1) / colblocks);
+    int chunks = (int)((target + colblocks - 1) / colblocks);
     if (chunks > d.nz) chunks = d.nz;
     if (chunks < 1) chunks = 1;
     a.zchunk = (d.nz + chunks - 1) / chunks;
-    chunks = (d.nz + a.zchunk - 1) / a.zchunk;
-    const dim3 g((unsigned)colblocks, (unsigned)chunks);
+    a.colblocks = (int)colblocks;
+    return a;
+}
+
+int z_blocks(const ZArgs& a)
+{
+    return a.colblocks * ((a.nz + a.zchunk - 1) / a.zchunk);
+}
+
+hipError_t launch_z(const float* q, float* out, Dims d, const GaussTaps& t, const int* stop, double* norms,
+                    hipStream_t st)
+{
+    ZArgs a = z_args(q, out, d, t);
+    a.stop = stop;
+    a.norms = norms;
+    const dim3 g((unsigned)z_blocks(a));
     switch (t.R) {
-#define DISC_R(RR) \
-    case RR: hipLaunchKernelGGL(k_smooth_z<RR>, g, dim3(ZNT), 0, st, a); break;
+#define DISC_R(RR)                                                                   \
+    case RR:                                                                         \
+        if (norms)                                                                   \
+            hipLaunchKernelGGL((k_smooth_z<RR, true>), g, dim3(ZNT), 0, st, a);      \
+        else                                                                         \
+            hipLaunchKernelGGL((k_smooth_z<RR, false>), g, dim3(ZNT), 0, st, a);     \
+        break;
         DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
 #undef DISC_R
         default: return hipErrorInvalidValue;
@@ -358,7 +521,8 @@ PlaneArgs plane_args(Dims d, const GaussTaps& t, int tx = PTX, int ty = PTY, int
 }  // namespace
 
 hipError_t launch_force_xy(const float* m, const float* f, const float* r, float* q, float* rt,
-                           Dims d, float eps_d, const GaussTaps& t, hipStream_t st)
+                           Dims d, float eps_d, int force_mode, const GaussTaps& t, const int* stop,
+                           hipStream_t st)
 {
     PlaneArgs a = plane_args(d, t);
     a.m = m;
@@ -366,8 +530,9 @@ hipError_t launch_force_xy(const float* m, const float* f, const float* r, float
     a.r = r;
     a.q = q;
     a.rt = rt;
+    a.stop = stop;
     a.eps_d = eps_d;
-    return launch_plane<true>(a, t.R, st);
+    return force_mode == 1 ? launch_plane<2>(a, t.R, st) : launch_plane<1>(a, t.R, st);
 }
 
 hipError_t launch_smooth_xy(const float* rt, float* q, Dims d, const GaussTaps& t, hipStream_t st)
@@ -375,12 +540,83 @@ hipError_t launch_smooth_xy(const float* rt, float* q, Dims d, const GaussTaps& 
     PlaneArgs a = plane_args(d, t);
     a.r = rt;
     a.q = q;
-    return launch_plane<false>(a, t.R, st);
+    a.stop = nullptr;
+    return launch_plane<0>(a, t.R, st);
 }
 
-hipError_t launch_smooth_z(const float* q, float* out, Dims d, const GaussTaps& t, hipStream_t st)
+hipError_t launch_smooth_z(const float* q, float* out, Dims d, const GaussTaps& t, const int* stop,
+                           double* norms, hipStream_t st)
 {
-    return launch_z(q, out, d, t, st);
+    return launch_z(q, out, d, t, stop, norms, st);
+}
+
+int smooth_z_blocks(Dims d)
+{
+    GaussTaps t{};
+    return z_blocks(z_args(nullptr, nullptr, d, t));
+}
+
+hipError_t launch_stop_rule(const double* norms, int nparts, double* hist, int* flags, int k, int lag,
+                            double eps, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stop_rule, dim3(1), dim3(256), 0, st, norms, nparts, hist, flags, k, lag, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_xy_batch(const BatchVol* vols, int n, float eps_d, int force_mode, const GaussTaps& t,
+                                 int target, hipStream_t st)
+{
+    if (n < 1 || n > kMaxBatch) return hipErrorInvalidValue;
+    Batch<PlaneArgs> b{};
+    b.n = n;
+    b.start[0] = 0;
+    for (int v = 0; v < n; ++v) {
+        PlaneArgs& a = b.v[v];
+        a = plane_args(vols[v].d, t, PTX, PTY, target);
+        a.m = vols[v].m;
+        a.f = vols[v].f;
+        a.r = vols[v].r;
+        a.q = vols[v].q;
+        a.rt = nullptr;
+        a.stop = nullptr;
+        a.eps_d = eps_d;
+        b.start[v + 1] = b.start[v] + a.nblocks;
+    }
+    const dim3 g((unsigned)b.start[n]);
+    switch (t.R) {
+#define DISC_R(RR)                                                                                       \
+    case RR:                                                                                             \
+        if (force_mode == 1)                                                                             \
+            hipLaunchKernelGGL((k_plane_xy_batch<RR, 2, PTX, PTY, PPIPE>), g, dim3(PTX * PTY), 0, st, b); \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_plane_xy_batch<RR, 1, PTX, PTY, PPIPE>), g, dim3(PTX * PTY), 0, st, b); \
+        break;
+        DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
+#undef DISC_R
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_z_batch(const BatchVol* vols, int n, const GaussTaps& t, int target, hipStream_t st)
+{
+    if (n < 1 || n > kMaxBatch) return hipErrorInvalidValue;
+    Batch<ZArgs> b{};
+    b.n = n;
+    b.start[0] = 0;
+    for (int v = 0; v < n; ++v) {
+        b.v[v] = z_args(vols[v].q, vols[v].r, vols[v].d, t, target);
+        b.start[v + 1] = b.start[v] + z_blocks(b.v[v]);
+    }
+    const dim3 g((unsigned)b.start[n]);
+    switch (t.R) {
+#define DISC_R(RR) \
+    case RR: hipLaunchKernelGGL(k_smooth_z_batch<RR>, g, dim3(ZNT), 0, st, b); break;
+        DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
+#undef DISC_R
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace disc

@@ -1,0 +1,115 @@
+"""Batched DISC on the GPU: uneven pairs advanced together.
+
+Each pair of a batch must give the field and corrected image of the
+single-volume path (levels = 1, same parameters) to the final-field bar
+(max 0.05, RMS 0.01 voxel), and one pair is compared with the FP64 oracle
+directly. Graph replay must equal eager launches bit for bit, also when the
+graph is replayed several times with other work in between.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.helpers import FIELD_MAX, FIELD_RMS, field_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(24, 40, 48), (17, 33, 29), (30, 26, 52)]
+PATCH, SIGMA, ITERS = (5, 5, 5), 1.5, 12
+
+
+@pytest.fixture(scope="module")
+def disc():
+    import paper_1204_6295_amd as d
+
+    d.lib()
+    return d
+
+
+@pytest.fixture(scope="module")
+def pairs():
+    from synth.phantom import make_ellipsoid_pair
+
+    out = []
+    for i, shp in enumerate(SHAPES):
+        c = make_ellipsoid_pair(shp, pair=100 + i, cid=1, device="cuda", max_def_vox=2.0)
+        out.append((c.ct, c.cbct))
+    return out
+
+
+def _single(disc, ct, cb, iters=ITERS):
+    reg = disc.Registration(patch=PATCH, sigma=SIGMA, levels=1, iters=(iters,))
+    reg.set_volumes(ct, cb)
+    reg.run()
+    return reg.field(), reg.corrected()
+
+
+@pytest.mark.parametrize("tiles", [dict(mom_ts=32, mom_target=256, plane_target=512, z_target=2048),
+                                   dict(mom_ts=16, mom_target=64, plane_target=64, z_target=128)])
+def test_batch_matches_single_volume_path(disc, pairs, tiles):
+    cts = [to_dev(p[0]) for p in pairs]
+    cbs = [to_dev(p[1]) for p in pairs]
+    b = disc.Batch(SHAPES, patch=PATCH, sigma=SIGMA, iters=ITERS)
+    b.set_tiles(**tiles)
+    b.set_volumes(cts, cbs)
+    b.run(use_graph=True)
+    for v in range(len(SHAPES)):
+        r1, f1 = _single(disc, cts[v], cbs[v])
+        rb, fb = b.field(v), b.corrected(v)
+        emax, erms = field_err(to_np(rb), to_np(r1))
+        frel = float((fb - f1).abs().max() / f1.abs().max())
+        print("pair %d %s: field max %.2g rms %.2g, I's rel %.2g, |r| max %.2f"
+              % (v, SHAPES[v], emax, erms, frel, float(r1.abs().max())))
+        assert emax <= FIELD_MAX and erms <= FIELD_RMS
+        assert frel <= 1e-4
+
+
+def test_batch_pair_matches_oracle(disc, pairs):
+    cts = [to_dev(p[0]) for p in pairs]
+    cbs = [to_dev(p[1]) for p in pairs]
+    b = disc.Batch(SHAPES, patch=PATCH, sigma=SIGMA, iters=ITERS)
+    b.set_volumes(cts, cbs)
+    b.run(use_graph=False)
+    v = 1
+    params = oracle.make_params(patch=PATCH, sigma=SIGMA, levels=1, iters=(ITERS,))
+    r_ref, _ = oracle.register(pairs[v][0].astype(np.float64), pairs[v][1].astype(np.float64), params)
+    emax, erms = field_err(to_np(b.field(v)), r_ref)
+    print("pair %d vs oracle: field max %.2g rms %.2g" % (v, emax, erms))
+    assert emax <= FIELD_MAX and erms <= FIELD_RMS
+
+
+def test_graph_replay_equals_eager(disc, pairs):
+    cts = [to_dev(p[0]) for p in pairs]
+    cbs = [to_dev(p[1]) for p in pairs]
+    eager = disc.Batch(SHAPES, patch=PATCH, sigma=SIGMA, iters=ITERS)
+    eager.set_volumes(cts, cbs)
+    graph = disc.Batch(SHAPES, patch=PATCH, sigma=SIGMA, iters=ITERS)
+    graph.set_volumes(cts, cbs)
+    for rep in range(3):
+        eager.iterate(4, use_graph=False)
+        graph.iterate(4, use_graph=True)
+        torch.cuda.synchronize()
+        # unrelated eager work between the replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        for v in range(len(SHAPES)):
+            assert bool((eager.field(v) == graph.field(v)).all()), (rep, v)
+            assert bool((eager.corrected(v) == graph.corrected(v)).all()), (rep, v)
+        del junk
+
+
+def test_autotuner_picks_and_caches(disc, pairs, tmp_path):
+    cts = [to_dev(p[0]) for p in pairs]
+    cbs = [to_dev(p[1]) for p in pairs]
+    b = disc.Batch(SHAPES, patch=PATCH, sigma=SIGMA, iters=ITERS)
+    cache = str(tmp_path / "tiles.json")
+    tiles, ms, hit = disc.autotune(b, cts, cbs, cache_path=cache, iters=2)
+    assert not hit and tiles in disc.TILE_CANDIDATES and ms > 0
+    b2 = disc.Batch(SHAPES, patch=PATCH, sigma=SIGMA, iters=ITERS)
+    tiles2, ms2, hit2 = disc.autotune(b2, cts, cbs, cache_path=cache)
+    assert hit2 and tiles2 == tiles and ms2 == ms
+    b2.run()
+    r1, _ = _single(disc, cts[0], cbs[0])
+    emax, erms = field_err(to_np(b2.field(0)), to_np(r1))
+    assert emax <= FIELD_MAX and erms <= FIELD_RMS

@@ -1,0 +1,96 @@
+"""Eq. 7-10 mask and fill on the GPU against the FP64 oracle.
+
+At set-up the device resolves the Sec. 2.3 rules (a_m, HU_0, h); one
+iteration from r = 0 then exercises the mask and every fill pass on known
+inputs (m = CT exactly), and whole registrations compare fields. Mask
+decisions are taken on FP32 data on both sides; the inputs keep every
+voxel's |m - S| and a away from the thresholds by much more than rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import FIELD_MAX, FIELD_RMS, field_err, rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def disc():
+    import paper_1204_6295_amd as d
+
+    d.lib()
+    return d
+
+
+def _c1():
+    from synth.phantom import make_case
+
+    c = make_case("c1")
+    return c.ct, c.cbct
+
+
+def test_mask_parameters_match_the_rules(disc):
+    ct, cb = _c1()
+    reg = disc.Registration(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(1,), mask_mode=1)
+    reg.set_volumes(to_dev(ct), to_dev(cb))
+    mp = reg.mask_params()
+    dhu, s = oracle.global_shift(ct, cb)
+    am = oracle.a_median(ct, s, (5, 5, 5))
+    print("GPU %s; oracle a_m %.6f, HU0 %.4f" % (mp, am, 2 * abs(dhu)))
+    assert abs(mp["a_m"] - am) <= 1e-6 * am
+    assert abs(mp["hu0"] - 2 * abs(dhu)) <= 1e-5 * abs(dhu)
+    assert abs(mp["a_min"] - 0.5 * am) <= 1e-6 * am and abs(mp["a_max"] - 1.5 * am) <= 1e-6 * am
+    assert mp["h"] == mp["hu0"]
+
+
+def test_first_iteration_mask_and_fill(disc):
+    """At r = 0 the deformed image is the CT itself, so the corrected image
+    of the first iteration is Eq. 5-10 on known inputs: GPU vs oracle."""
+    ct, cb = _c1()
+    reg = disc.Registration(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(1,), mask_mode=1)
+    reg.set_volumes(to_dev(ct), to_dev(cb))
+    reg.run()
+    f = to_np(reg.corrected())
+    mp = reg.mask_params()
+    _, s = oracle.global_shift(ct, cb)
+    s32 = s.astype(np.float32).astype(np.float64)
+    A, B, xi, used = oracle.mask_fill(ct, s32, (5, 5, 5), 1e-2, mp["hu0"], mp["a_min"], mp["a_max"], mp["h"],
+                                      t=(7, 7, 3), passes=10)
+    f_ref = A * s32 + B
+    err = np.abs(f - f_ref)
+    print("masked %.3f, passes %d, max |f - ref| %.3g HU, rel %.3g" % (xi.mean(), used, err.max(),
+                                                                       rel_err(f, f_ref)))
+    assert 0.05 < xi.mean() < 0.95 and used >= 2
+    assert rel_err(f, f_ref) <= 1e-4
+
+
+def test_masked_registration_matches_oracle(disc):
+    ct, cb = _c1()
+    kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,), mask_mode=1)
+    reg = disc.Registration(**kw)
+    reg.set_volumes(to_dev(ct), to_dev(cb))
+    reg.run()
+    r_ref, f_ref = oracle.register(ct, cb, oracle.make_params(**kw))
+    emax, erms = field_err(to_np(reg.field()), r_ref)
+    print("masked c1: field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
+    assert emax <= FIELD_MAX and erms <= FIELD_RMS
+    assert rel_err(to_np(reg.corrected()), f_ref) <= 1e-3
+
+
+def test_masked_pyramid_and_determinism(disc):
+    from synth.phantom import make_hn_pair
+
+    c = make_hn_pair((24, 64, 64), pair=2)
+    kw = dict(patch=(7, 7, 5), sigma=2.0, levels=2, iters=(8, 6), mask_mode=1, fill_passes=6)
+    outs = []
+    for _ in range(2):
+        reg = disc.Registration(**kw)
+        reg.set_volumes(to_dev(c.ct), to_dev(c.cbct))
+        reg.run()
+        outs.append((to_np(reg.field()), to_np(reg.corrected())))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    r_ref, f_ref = oracle.register(c.ct, c.cbct, oracle.make_params(**kw))
+    emax, erms = field_err(outs[0][0], r_ref)
+    print("masked pyramid: field err max %.3g rms %.3g" % (emax, erms))
+    assert emax <= FIELD_MAX and erms <= FIELD_RMS
