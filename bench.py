@@ -46,6 +46,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per finest-level launch of `kernel` from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is none for this
+    kernel and workload, or the kernel's sources have changed since the
+    counters were taken (sha256 recorded with the summary)."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_b = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    m_h = re.search(r"^traffic_source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    if not (m_b and m_h):
+        return None
+    h = hashlib.sha256()
+    for rel in ("smooth.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1204_6295_amd", "csrc", rel), "rb") as fh:
+            h.update(fh.read())
+    return int(m_b.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
 def _ms_per_call(fn, reps, warm=2):
     import torch
 
@@ -260,15 +283,16 @@ def main():
             if n:
                 kernels[name] = dict(launches=n, total_ms=ms, avg_us=1000.0 * ms / n,
                                      gbs=BYTES_PER_VOXEL[name] * vox / (ms * 1e-3) / 1e9)
+        # dominant kernel by total time; its roofline per finest-level launch
         dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-        k = kernels[dom]
-        n, ms, vox = reg.timing_read(dom)
-        achieved = BYTES_PER_VOXEL[dom] * vox / n / (ms / n * 1e-3) / 1e9
+        n, ms, vox = reg.timing_read(dom, cfg["levels"] - 1)
+        avg_s = ms / n * 1e-3
+        achieved = BYTES_PER_VOXEL[dom] * (vox / n) / avg_s / 1e9
         roofline = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": dom, "avg_launch_us": round(k["avg_us"], 2), "launches": n,
-            "bytes_per_voxel": BYTES_PER_VOXEL[dom],
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, args.workload),
+            "kernel": dom, "level": "finest", "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
+            "bytes_per_voxel": BYTES_PER_VOXEL[dom], "voxels_per_launch": vox / n,
         }
         for name, kk in kernels.items():
             log("  %-9s launches %5d  avg %8.2f us  %7.1f GB/s  share %.1f%%" % (
