@@ -30,7 +30,7 @@ BYTES_PER_VOXEL = {
     "warp": 20.0,      # r 12 + CT 4 + m 4
     "correct": 12.0,   # m 4 + ys 4 + f 4
     "force_xy": 32.0,  # m 4 + f 4 + r 12 + xy-filtered r~ 12
-    "smooth_z": 24.0,  # xy-filtered r~ 12 + r 12
+    "smooth_z": 32.0,  # xy-filtered r~ 12 + r 12, and the next warp: CT 4 + m 4
     "upsample": 13.5,  # fine r 12 + coarse r 12/8, per fine voxel
 }
 ALGORITHMIC_MIN_BYTES = 32.0  # read CT, CBCT, r; write r (whole iteration)
@@ -334,6 +334,7 @@ def main():
     if roofline is not None:
         out["roofline"] = roofline
     if not args.no_extras:
+        reg.timing_enable(0)  # no event pairs in the remaining measurements
         fin = finest_level_rate(reg, ct, cb, cfg)
         log("finest level alone: %.3f ms for %d iterations, %.3g voxel-it/s" % (
             fin["ms"], fin["iterations"], fin["voxel_iterations_per_s"]))

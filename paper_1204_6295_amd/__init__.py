@@ -474,7 +474,7 @@ class Batch:
             m = lib().disc_batch_last_error(self._h)
             raise DiscError(rc, m.decode() if m else "")
 
-    def set_tiles(self, mom_ts=32, mom_target=256, plane_target=512, z_target=2048):
+    def set_tiles(self, mom_ts=32, mom_target=256, plane_target=256, z_target=8192):
         self._check(lib().disc_batch_set_tiles(self._h, int(mom_ts), int(mom_target), int(plane_target),
                                                int(z_target)))
 
@@ -512,11 +512,12 @@ class Batch:
 
 # Launch-knob candidates of the batched iteration, tried by the autotuner.
 TILE_CANDIDATES = [
+    dict(mom_ts=32, mom_target=256, plane_target=256, z_target=8192),
     dict(mom_ts=32, mom_target=256, plane_target=512, z_target=2048),
     dict(mom_ts=32, mom_target=128, plane_target=256, z_target=1024),
     dict(mom_ts=32, mom_target=512, plane_target=1024, z_target=4096),
     dict(mom_ts=16, mom_target=256, plane_target=512, z_target=2048),
-    dict(mom_ts=16, mom_target=1024, plane_target=1024, z_target=4096),
+    dict(mom_ts=16, mom_target=1024, plane_target=1024, z_target=8192),
 ]
 
 

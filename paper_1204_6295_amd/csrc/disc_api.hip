@@ -62,6 +62,7 @@ struct disc_ctx {
     int it = 0;
     bool ready = false;
     bool f_valid = false;
+    bool m_ready = false;  // m holds CT(x + r(x)) for the current field
     std::string err;
     // event timing
     int max_rec = 0;
@@ -263,6 +264,7 @@ int one_iteration(disc_ctx* c, hipStream_t st)
         c->level += 1;
         c->it = 0;
         c->f_valid = false;
+        c->m_ready = false;
     }
     const int l = c->level;
     const Dims d = c->dims[l];
@@ -276,11 +278,16 @@ int one_iteration(disc_ctx* c, hipStream_t st)
     // the history holds hist_stride >= iters[l] entries: iterations past the
     // schedule (finest level) run without evaluating the rule again
     const bool record = rule && c->it < c->hist_stride;
-    {
-        Timed tm(c, st, K_WARP, l, vox);
-        e = disc::launch_warp(c->ct[l], r, c->m, d, st, flags);
+    // the z pass of the previous iteration has already warped the CT with
+    // the field it produced; a standalone warp is needed only after set-up,
+    // a level switch or disc_set_field
+    if (!c->m_ready) {
+        {
+            Timed tm(c, st, K_WARP, l, vox);
+            e = disc::launch_warp(c->ct[l], r, c->m, d, st, flags);
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "warp");
     }
-    if (e != hipSuccess) return hip_fail(c, e, "warp");
     if (c->p.mask_mode == 1) {
         {
             Timed tm(c, st, K_CORRECT, l, vox);
@@ -311,7 +318,7 @@ int one_iteration(disc_ctx* c, hipStream_t st)
     if (e != hipSuccess) return hip_fail(c, e, "force + xy smoothing");
     {
         Timed tm(c, st, K_SMOOTH_Z, l, vox);
-        e = disc::launch_smooth_z(q, r, d, c->taps, flags, record ? c->norms : nullptr, st);
+        e = disc::launch_smooth_z(q, r, d, c->taps, flags, record ? c->norms : nullptr, st, c->ct[l], c->m);
     }
     if (e != hipSuccess) return hip_fail(c, e, "z smoothing");
     if (record) {
@@ -321,6 +328,7 @@ int one_iteration(disc_ctx* c, hipStream_t st)
     }
     c->it += 1;
     c->f_valid = true;
+    c->m_ready = true;
     return DISC_OK;
 }
 
@@ -460,6 +468,7 @@ int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev, in
     c->level = 0;
     c->it = 0;
     c->f_valid = false;
+    c->m_ready = false;
     c->ready = true;
     return DISC_OK;
 }
@@ -523,6 +532,7 @@ int disc_set_field(disc_ctx* c, const float* r_dev, void* stream)
     hipError_t e = hipMemcpyAsync(c->r[c->cur], r_dev, (size_t)d.n() * 12, hipMemcpyDeviceToDevice,
                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "copy field");
+    c->m_ready = false;
     return DISC_OK;
 }
 
@@ -929,7 +939,7 @@ int disc_batch_create(const disc_params* p, int n, const int* dims, disc_batch**
     }
     b->vols.resize(n);
     b->s.resize(n);
-    b->tiles = disc::BatchTiles{32, 256, 512, 2048};
+    b->tiles = disc::BatchTiles{32, 256, 256, 8192};
     *out = b;
     return DISC_OK;
 }

@@ -57,11 +57,12 @@ hipError_t launch_force_xy(const float* m, const float* f, const float* r, float
 // q = G_xy * rt (x and y passes only).
 hipError_t launch_smooth_xy(const float* rt, float* q, Dims d, const GaussTaps& t, hipStream_t st);
 
-// out = G_z * q (z pass). norms (may be null): out holds r^(k) on entry and
+// out = G_z * q (z pass). ct and m (both or neither): also m = CT(x + out(x))
+// at every output voxel, the next iteration's warp. norms (may be null): out holds r^(k) on entry and
 // each workgroup writes (sum |r^(k+1) - r^(k)|, sum |r^(k)|) in FP64 to
 // norms[2 b], norms[2 b + 1], b < smooth_z_blocks(d).
 hipError_t launch_smooth_z(const float* q, float* out, Dims d, const GaussTaps& t, const int* stop,
-                           double* norms, hipStream_t st);
+                           double* norms, hipStream_t st, const float* ct = nullptr, float* m = nullptr);
 int smooth_z_blocks(Dims d);
 // Sec. 2.3 stopping rule after iteration k (see k_stop_rule).
 hipError_t launch_stop_rule(const double* norms, int nparts, double* hist, int* flags, int k, int lag,
@@ -124,6 +125,42 @@ __device__ inline int xcd_logical_block(int bid, int nblocks)
 __device__ inline int clampi(int v, int n)
 {
     return v < 0 ? 0 : (v > n - 1 ? n - 1 : v);
+}
+
+// Keeps float->int conversions in range for any input (NaN/Inf included);
+// the clamped voxel index then always lies inside the volume.
+__device__ inline int floor_to_int(float v)
+{
+    float f = floorf(v);
+    f = fminf(fmaxf(f, -1048576.0f), 1048576.0f);
+    return (int)f;
+}
+
+// Sec. 2.1 model I_m(x + v(x)) = I_s(x): the deformed moving image at x is the
+// CT sampled at x + r(x), trilinear, corner indices clamped. The weights come
+// from the fractional part of r alone and the integer voxel is added
+// separately, so FP32 keeps the full sub-voxel resolution at any volume size.
+// Shared by the warp kernel and the z-smoothing kernel (which warps with the
+// field it has just produced), so both give bitwise the same m.
+__device__ inline float warp_at(const float* __restrict__ ct, int x, int y, int z, float rx,
+                                float ry, float rz, int nx, int ny, int nz)
+{
+    const float tx = rx - floorf(rx), ty = ry - floorf(ry), tz = rz - floorf(rz);
+    const int ix = x + floor_to_int(rx), iy = y + floor_to_int(ry), iz = z + floor_to_int(rz);
+    const int x0 = clampi(ix, nx), x1 = clampi(ix + 1, nx);
+    const int y0 = clampi(iy, ny), y1 = clampi(iy + 1, ny);
+    const int z0 = clampi(iz, nz), z1 = clampi(iz + 1, nz);
+    const float* p00 = ct + ((long)z0 * ny + y0) * nx;
+    const float* p01 = ct + ((long)z0 * ny + y1) * nx;
+    const float* p10 = ct + ((long)z1 * ny + y0) * nx;
+    const float* p11 = ct + ((long)z1 * ny + y1) * nx;
+    const float c00 = fmaf(tx, p00[x1] - p00[x0], p00[x0]);
+    const float c01 = fmaf(tx, p01[x1] - p01[x0], p01[x0]);
+    const float c10 = fmaf(tx, p10[x1] - p10[x0], p10[x0]);
+    const float c11 = fmaf(tx, p11[x1] - p11[x0], p11[x0]);
+    const float c0 = fmaf(ty, c01 - c00, c00);
+    const float c1 = fmaf(ty, c11 - c10, c10);
+    return fmaf(tz, c1 - c0, c0);
 }
 
 // ---- batches of volumes in one launch --------------------------------------

@@ -22,40 +22,6 @@ inline dim3 grid_for(Dims d)
     return dim3((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz);
 }
 
-// Keeps float->int conversions in range for any input (NaN/Inf included);
-// the clamped voxel index then always lies inside the volume.
-__device__ inline int floor_to_int(float v)
-{
-    float f = floorf(v);
-    f = fminf(fmaxf(f, -1048576.0f), 1048576.0f);
-    return (int)f;
-}
-
-// Sec. 2.1 model I_m(x + v(x)) = I_s(x): the deformed moving image at x is the
-// CT sampled at x + r(x). The weights come from the fractional part of r
-// alone and the integer voxel is added separately, so FP32 keeps the full
-// sub-voxel resolution at any volume size.
-__device__ inline float warp_at(const float* __restrict__ ct, int x, int y, int z, float rx,
-                                float ry, float rz, int nx, int ny, int nz)
-{
-    const float tx = rx - floorf(rx), ty = ry - floorf(ry), tz = rz - floorf(rz);
-    const int ix = x + floor_to_int(rx), iy = y + floor_to_int(ry), iz = z + floor_to_int(rz);
-    const int x0 = clampi(ix, nx), x1 = clampi(ix + 1, nx);
-    const int y0 = clampi(iy, ny), y1 = clampi(iy + 1, ny);
-    const int z0 = clampi(iz, nz), z1 = clampi(iz + 1, nz);
-    const float* p00 = ct + ((long)z0 * ny + y0) * nx;
-    const float* p01 = ct + ((long)z0 * ny + y1) * nx;
-    const float* p10 = ct + ((long)z1 * ny + y0) * nx;
-    const float* p11 = ct + ((long)z1 * ny + y1) * nx;
-    const float c00 = fmaf(tx, p00[x1] - p00[x0], p00[x0]);
-    const float c01 = fmaf(tx, p01[x1] - p01[x0], p01[x0]);
-    const float c10 = fmaf(tx, p10[x1] - p10[x0], p10[x0]);
-    const float c11 = fmaf(tx, p11[x1] - p11[x0], p11[x0]);
-    const float c0 = fmaf(ty, c01 - c00, c00);
-    const float c1 = fmaf(ty, c11 - c10, c10);
-    return fmaf(tz, c1 - c0, c0);
-}
-
 // Two rows per thread (y and y + BY) so that each thread has six field loads
 // and sixteen corner gathers in flight. (bx, by, z) is the workgroup's tile.
 __device__ inline void warp_body(const float* __restrict__ ct, const float* __restrict__ r,

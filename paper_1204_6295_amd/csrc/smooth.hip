@@ -287,6 +287,8 @@ struct ZArgs {
     float* out;
     const int* stop;  // level's stop flag (stopping rule), may be null
     double* norms;    // NORM: per workgroup (sum |r_new - r_old|, sum |r_old|)
+    const float* ct;  // WARP: the CT warped with the new field ...
+    float* m;         // ... into m, the next iteration's deformed moving image
     int nx, ny, nz;
     int zchunk;
     int colblocks;  // workgroups across the columns of one z chunk
@@ -300,7 +302,7 @@ constexpr int ZNT = 256;
 // block. NORM: out holds r^(k) on entry; the workgroup also sums, in FP64,
 // the Euclidean norms of r^(k+1) - r^(k) and of r^(k) over its voxels (the
 // two sums of l^(k), Sec. 2.3).
-template <int R, bool NORM>
+template <int R, bool NORM, bool WARP>
 __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
 {
     constexpr int K = 2 * R + 1;
@@ -351,6 +353,9 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
                 if (act) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) a.out[c * N + o] = nv[c];
+                    if (WARP)
+                        a.m[o] = warp_at(a.ct, (int)(col % a.nx), (int)(col / a.nx), z0 + p - 2 * R, nv[0], nv[1],
+                                         nv[2], a.nx, a.ny, a.nz);
                 }
                 if (NORM && act) {
                     const float dx = nv[0] - ov[0], dy = nv[1] - ov[1], dz = nv[2] - ov[2];
@@ -381,17 +386,17 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
     }
 }
 
-template <int R, bool NORM>
+template <int R, bool NORM, bool WARP>
 __global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
 {
-    smooth_z_body<R, NORM>(a, blockIdx.x);
+    smooth_z_body<R, NORM, WARP>(a, blockIdx.x);
 }
 
 template <int R>
 __global__ __launch_bounds__(ZNT) void k_smooth_z_batch(Batch<ZArgs> b)
 {
     const int v = batch_volume(b.start, b.n, blockIdx.x);
-    smooth_z_body<R, false>(b.v[v], blockIdx.x - b.start[v]);
+    smooth_z_body<R, false, false>(b.v[v], blockIdx.x - b.start[v]);
 }
 
 // Sec. 2.3 stopping rule after iteration k of a level: l^(k) = sum |dr| /
@@ -448,15 +453,18 @@ hipError_t launch_plane(const PlaneArgs& a, int R, hipStream_t st)
     return hipGetLastError();
 }
 
-// z chunks: about `target` workgroups in the launch; re-read halo planes
-// come from cache.
-ZArgs z_args(const float* q, float* out, Dims d, const GaussTaps& t, int target = 2048)
+// z chunks: about `target` workgroups in the launch (measured best at 8192
+// for the 256x256x96 registration: the fused warp's gathers want many waves
+// in flight); re-read halo planes come from cache.
+ZArgs z_args(const float* q, float* out, Dims d, const GaussTaps& t, int target = 8192)
 {
     ZArgs a;
     a.q = q;
     a.out = out;
     a.stop = nullptr;
     a.norms = nullptr;
+    a.ct = nullptr;
+    a.m = nullptr;
     a.nx = d.nx;
     a.ny = d.ny;
     a.nz = d.nz;
@@ -477,19 +485,26 @@ int z_blocks(const ZArgs& a)
 }
 
 hipError_t launch_z(const float* q, float* out, Dims d, const GaussTaps& t, const int* stop, double* norms,
-                    hipStream_t st)
+                    const float* ct, float* m, hipStream_t st)
 {
     ZArgs a = z_args(q, out, d, t);
     a.stop = stop;
     a.norms = norms;
+    a.ct = ct;
+    a.m = m;
+    const bool w = ct && m;
     const dim3 g((unsigned)z_blocks(a));
     switch (t.R) {
-#define DISC_R(RR)                                                                   \
-    case RR:                                                                         \
-        if (norms)                                                                   \
-            hipLaunchKernelGGL((k_smooth_z<RR, true>), g, dim3(ZNT), 0, st, a);      \
-        else                                                                         \
-            hipLaunchKernelGGL((k_smooth_z<RR, false>), g, dim3(ZNT), 0, st, a);     \
+#define DISC_R(RR)                                                                          \
+    case RR:                                                                                \
+        if (norms && w)                                                                     \
+            hipLaunchKernelGGL((k_smooth_z<RR, true, true>), g, dim3(ZNT), 0, st, a);       \
+        else if (norms)                                                                     \
+            hipLaunchKernelGGL((k_smooth_z<RR, true, false>), g, dim3(ZNT), 0, st, a);      \
+        else if (w)                                                                         \
+            hipLaunchKernelGGL((k_smooth_z<RR, false, true>), g, dim3(ZNT), 0, st, a);      \
+        else                                                                                \
+            hipLaunchKernelGGL((k_smooth_z<RR, false, false>), g, dim3(ZNT), 0, st, a);     \
         break;
         DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
 #undef DISC_R
@@ -498,7 +513,9 @@ hipError_t launch_z(const float* q, float* out, Dims d, const GaussTaps& t, cons
     return hipGetLastError();
 }
 
-PlaneArgs plane_args(Dims d, const GaussTaps& t, int tx = PTX, int ty = PTY, int target = 512)
+// about `target` workgroups (measured best at 256: one 1024-thread workgroup
+// per CU, longer z chunks)
+PlaneArgs plane_args(Dims d, const GaussTaps& t, int tx = PTX, int ty = PTY, int target = 256)
 {
     PlaneArgs a{};
     a.nx = d.nx;
@@ -545,9 +562,9 @@ hipError_t launch_smooth_xy(const float* rt, float* q, Dims d, const GaussTaps& 
 }
 
 hipError_t launch_smooth_z(const float* q, float* out, Dims d, const GaussTaps& t, const int* stop,
-                           double* norms, hipStream_t st)
+                           double* norms, hipStream_t st, const float* ct, float* m)
 {
-    return launch_z(q, out, d, t, stop, norms, st);
+    return launch_z(q, out, d, t, stop, norms, ct, m, st);
 }
 
 int smooth_z_blocks(Dims d)

@@ -61,15 +61,6 @@ __global__ __launch_bounds__(BX* BY) void k_box_adjoint(const double2* __restric
     out[i] = make_double2(s1, s2);
 }
 
-// Keeps float->int conversions in range for any input; the clamped corner
-// index then always lies inside the volume.
-__device__ inline int floor_to_int(float v)
-{
-    float f = floorf(v);
-    f = fminf(fmaxf(f, -1048576.0f), 1048576.0f);
-    return (int)f;
-}
-
 // dL/dr = dL/dm * d m / d position, with dL/dm = 2 D - 2 (m B(beta) + B(gamma))
 // and the derivative of the trilinear interpolant of the warp (same floor
 // and clamp conventions: the cell is the one the warp samples).
