@@ -346,6 +346,188 @@ __global__ __launch_bounds__(TS* TS) void k_moments_batch(Batch<MomArgs> b)
     moments_body<PZ, RXY, MODE, TS>(b.v[v], blockIdx.x - b.start[v]);
 }
 
+// ---- small volumes: several planes per step ------------------------------
+// Coarse pyramid levels have few tiles, so the plane-serial sweep above is
+// bound by the latency of its per-plane steps. Here a 1024-thread workgroup
+// owns a 16 x 16 column tile and takes PP = 4 planes per step, one plane per
+// 256-thread group: the group stages its plane, runs the x and y window sums,
+// and stores the plane's y sums in an LDS ring of the last PZ + PP - 1
+// planes; every thread then forms one output (its column, one of the PP
+// window ends of the step) as the direct FP64 sum of PZ ring entries.
+constexpr int PPS = 4;       // planes per step
+constexpr int PTS = 16;      // tile edge
+constexpr int PG = PTS * PTS;  // threads per plane group
+
+template <int PZ, int RXY>
+struct PpLds {
+    static constexpr int H = PTS + 2 * RXY;
+    static constexpr int PW = (H + 3) & ~3;
+    static constexpr int PXH = H | 1;
+    static constexpr int RING = PZ + PPS - 1;
+    static constexpr size_t M_BYTES = (size_t)PPS * H * PW * sizeof(float);
+    static constexpr size_t X_BYTES = (size_t)PPS * PTS * PXH * sizeof(double2);
+    static constexpr size_t Y_BYTES = (size_t)RING * PG * sizeof(double2);
+    static constexpr size_t BYTES = M_BYTES + X_BYTES + Y_BYTES;
+};
+
+template <int MODE>
+__device__ inline void mom_epilogue(const MomArgs& a, long idx, double mu, double var, float epi_v)
+{
+    if (MODE == kStatic) {
+        const double sv = (double)epi_v;
+        const bool flat = !(var > (double)a.tau);
+        const double yv = flat ? (sv - mu) : (sv - mu) / sqrt(var);
+        unsigned bits = __float_as_uint((float)yv);
+        bits = flat ? (bits | 1u) : (bits & ~1u);
+        a.out[idx] = __uint_as_float(bits);
+        if (a.sd_out) a.sd_out[idx] = flat ? 0.0f : (float)sqrt(var);
+    } else {
+        const double c = (__float_as_uint(epi_v) & 1u) ? 1.0 : (double)sqrtf((float)var);
+        a.out[idx] = (float)fma(c, (double)epi_v, mu);
+    }
+}
+
+template <int PZ, int RXY, int MODE>
+__global__ __launch_bounds__(PPS* PG) void k_moments_pp(MomArgs a)
+{
+    static_assert(RXY >= 0 && (MODE == kCorrect || MODE == kStatic), "isotropic correction / static only");
+    using L = PpLds<PZ, RXY>;
+    constexpr int H = L::H, PW = L::PW, PXH = L::PXH, RING = L::RING;
+    constexpr int RZ = PZ / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* s_m = reinterpret_cast<float*>(smem);
+    double2* s_x = reinterpret_cast<double2*>(smem + L::M_BYTES);
+    double2* s_y = reinterpret_cast<double2*>(smem + L::M_BYTES + L::X_BYTES);
+    if (a.stop && *a.stop) return;
+
+    const int lb = xcd_logical_block(blockIdx.x, a.nblocks);
+    const int bx = lb % a.tiles_x;
+    const int rest = lb / a.tiles_x;
+    const int by = rest % a.tiles_y;
+    const int bz = rest / a.tiles_y;
+    const int x0 = bx * PTS, y0 = by * PTS, z0 = bz * a.zchunk;
+    const int z1 = min(a.nz, z0 + a.zchunk);
+    const int t = threadIdx.x, grp = t / PG, tl = t % PG;
+    const int lx = tl % PTS, ly = tl / PTS;
+    const int ox = x0 + lx, oy = y0 + ly;
+    const bool own = ox < a.nx && oy < a.ny;
+    const long plane = (long)a.nx * a.ny;
+    const long col_off = (long)min(oy, a.ny - 1) * a.nx + min(ox, a.nx - 1);
+    const float* epi = MODE == kStatic ? a.img : a.ys_in;
+    const int nplanes = (z1 - z0) + 2 * RZ;
+    float* sm = s_m + grp * (H * PW);
+    double2* sx = s_x + grp * (PTS * PXH);
+
+    // the group's region points, fixed over the sweep; out-of-region slots
+    // load a valid address and are never stored (branch-free prefetch)
+    constexpr int NQ = (H * H + PG - 1) / PG;
+    int goff[NQ], soff[NQ];
+    bool gval[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = tl + q * PG;
+        const int row = i / H, col = i - row * H;
+        gval[q] = row < H;
+        goff[q] = gval[q] ? clampi(y0 - RXY + row, a.ny) * a.nx + clampi(x0 - RXY + col, a.nx) : 0;
+        soff[q] = gval[q] ? row * PW + col : 0;
+    }
+    float pre[NQ];
+    auto fetch = [&](int pl) {
+        const float* src = a.img + (long)clampi(z0 - RZ + min(pl, nplanes - 1), a.nz) * plane;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) pre[q] = src[goff[q]];
+    };
+    fetch(grp);
+
+    for (int p0 = 0; p0 < nplanes; p0 += PPS) {
+        const int p = p0 + grp;  // this group's plane
+        const bool live = p < nplanes;
+        // the epilogue input of this step's output, requested before the passes
+        const long idx = (long)clampi(z0 + p - 2 * RZ, a.nz) * plane + col_off;
+        const float epi_v = epi[idx];
+        // stash the prefetched plane, then request the group's next one
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (gval[q]) sm[soff[q]] = pre[q];
+        }
+        fetch(p + PPS);
+        __syncthreads();
+        // x pass: one item per (row, run of 4 columns)
+        if (live) {
+            for (int i = tl; i < H * (PTS / RUN); i += PG) {
+                const int row = i % H, run = i / H;
+                window_x<RXY>(sm + row * PW + run * RUN, RXY, sx + run * RUN * PXH + row, PXH);
+            }
+        }
+        __syncthreads();
+        // y pass: one item per (column, run of 4 rows), into the ring slot of plane p
+        if (live && tl < PTS * (PTS / RUN)) {
+            const int col = tl % PTS, run = tl / PTS;
+            const double2* xs = sx + col * PXH + run * RUN;
+            double2* ys = s_y + (p % RING) * PG + run * RUN * PTS + col;
+            double u1 = 0.0, u2 = 0.0;
+#pragma unroll
+            for (int j = 0; j <= 2 * RXY; ++j) {
+                const double2 v = xs[j];
+                u1 += v.x;
+                u2 += v.y;
+            }
+            ys[0] = make_double2(u1, u2);
+#pragma unroll
+            for (int rr = 1; rr < RUN; ++rr) {
+                const double2 vi = xs[rr + 2 * RXY], vo = xs[rr - 1];
+                u1 += vi.x - vo.x;
+                u2 += vi.y - vo.y;
+                ys[rr * PTS] = make_double2(u1, u2);
+            }
+        }
+        __syncthreads();
+        // z: the window ending at plane e = p (planes e - PZ + 1 .. e)
+        if (live && p >= PZ - 1 && own) {
+            double z1s = 0.0, z2s = 0.0;
+#pragma unroll
+            for (int k = 0; k < PZ; ++k) {
+                const double2 v = s_y[((p - k) % RING) * PG + tl];
+                z1s += v.x;
+                z2s += v.y;
+            }
+            const double mu = z1s * a.inv_n;
+            double var = z2s * a.inv_n - mu * mu;
+            var = var > 0.0 ? var : 0.0;
+            mom_epilogue<MODE>(a, idx, mu, var, epi_v);
+        }
+        __syncthreads();
+    }
+}
+
+template <int PZ, int MODE>
+void launch_pp_kernel(const MomArgs& a, hipStream_t st)
+{
+    constexpr size_t lds = PpLds<PZ, PZ / 2>::BYTES;
+    static_assert(lds <= 160 * 1024, "fits the LDS of one CU");
+    static bool attr = false;
+    if (!attr && lds > 65536) {
+        (void)hipFuncSetAttribute((const void*)k_moments_pp<PZ, PZ / 2, MODE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_moments_pp<PZ, PZ / 2, MODE>), dim3(a.nblocks), dim3(PPS * PG), lds, st, a);
+}
+
+template <int MODE>
+hipError_t launch_pp(int pz, hipStream_t st, const MomArgs& a)
+{
+    switch (pz) {
+#define DISC_PZ(P) \
+    case P: launch_pp_kernel<P, MODE>(a, st); break;
+        DISC_PZ(1) DISC_PZ(3) DISC_PZ(5) DISC_PZ(7) DISC_PZ(9) DISC_PZ(11) DISC_PZ(13) DISC_PZ(15)
+#undef DISC_PZ
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int PZ, int RXY, int MODE, int TS>
 void launch_kernel(const MomArgs& a, hipStream_t st)
 {
@@ -454,6 +636,16 @@ hipError_t launch_moments(const float* img, const float* ys_in, float* out, doub
     a.tau = tau;
     a.inv_n = 1.0 / ((double)patch[0] * patch[1] * patch[2]);
     const MomGrid g = mom_grid(d);
+    const bool iso = patch[0] == patch[2] && patch[1] == patch[2];
+    if (g.TS == 16 && iso && (MODE == kCorrect || MODE == kStatic)) {
+        // small volume: several planes per step, about one workgroup per CU
+        const MomGrid gp = mom_grid_for(d, PTS, 256, 1);
+        a.tiles_x = gp.tiles_x;
+        a.tiles_y = gp.tiles_y;
+        a.zchunk = gp.zchunk;
+        a.nblocks = gp.nblocks;
+        return launch_pp<MODE == kStatic ? kStatic : kCorrect>(patch[2], st, a);
+    }
     a.tiles_x = g.tiles_x;
     a.tiles_y = g.tiles_y;
     a.zchunk = g.zchunk;
