@@ -150,10 +150,11 @@ __device__ inline float warp_at(const float* __restrict__ ct, int x, int y, int 
     const int x0 = clampi(ix, nx), x1 = clampi(ix + 1, nx);
     const int y0 = clampi(iy, ny), y1 = clampi(iy + 1, ny);
     const int z0 = clampi(iz, nz), z1 = clampi(iz + 1, nz);
-    const float* p00 = ct + ((long)z0 * ny + y0) * nx;
-    const float* p01 = ct + ((long)z0 * ny + y1) * nx;
-    const float* p10 = ct + ((long)z1 * ny + y0) * nx;
-    const float* p11 = ct + ((long)z1 * ny + y1) * nx;
+    // element offsets fit in 32 bits (the ABI bounds N below 2^31)
+    const float* p00 = ct + (z0 * ny + y0) * nx;
+    const float* p01 = ct + (z0 * ny + y1) * nx;
+    const float* p10 = ct + (z1 * ny + y0) * nx;
+    const float* p11 = ct + (z1 * ny + y1) * nx;
     const float c00 = fmaf(tx, p00[x1] - p00[x0], p00[x0]);
     const float c01 = fmaf(tx, p01[x1] - p01[x0], p01[x0]);
     const float c10 = fmaf(tx, p10[x1] - p10[x0], p10[x0]);

@@ -1,16 +1,17 @@
 // Eq. 1 force, the Algorithm A1 step-5 update and the step-6 Gaussian
 // regularisation of the displacement field, as two kernels for gfx950:
 //
-//   k_plane_xy  one workgroup per 32 x 32 tile and chunk of z planes. It forms
-//               r~ = r - u on the tile plus the R-voxel Gaussian halo
-//               (R = ceil(3 sigma)), u being the static-gradient demons force
-//               on the corrected image f (the f plane is staged in LDS for
-//               the in-plane gradient), then runs the x and y passes out of
-//               LDS with register-blocked runs of 4 outputs and writes the
-//               xy-filtered field q. The next plane's global loads are
-//               issued before the current plane's LDS work.
+//   k_plane_pipe  one workgroup per 32 x 32 tile and chunk of z planes. It
+//               forms r~ = r - u on the tile plus the R-voxel Gaussian halo
+//               (R = ceil(3 sigma)), u being the Eq. 1 demons force on the
+//               corrected image f (the f plane is staged in LDS for the
+//               in-plane gradient), then runs the x and y passes out of LDS
+//               with register-blocked runs of 4 outputs and writes the
+//               xy-filtered field q; the four stages are software-pipelined
+//               over planes.
 //   k_smooth_z  one thread per (x, y) column over a chunk of z: a register
-//               ring of the last 2R + 1 planes of q gives the z pass. Halo
+//               ring of the last 2R + 1 planes of q gives the z pass, and the
+//               CT is warped with the new field for the next iteration. Halo
 //               planes of a chunk are only re-read, never re-filtered.
 //
 // Splitting at the xy / z boundary keeps every filter pass free of
@@ -39,58 +40,79 @@ struct PlaneArgs {
     GaussTaps taps;
 };
 
-// One workgroup's z chunk of one column tile; bid is its workgroup index
-// within the volume.
+// ---- force + xy smoothing, software-pipelined over planes ------------------
 // FM: 0 smoothing only, 1 Eq. 1 static-gradient force, 2 both Eq. 1 terms.
-template <int R, int FM, int TX, int TY, bool PIPE>
-__device__ __forceinline__ void plane_body(const PlaneArgs& a, const int bid)
+// A workgroup owns a 32 x 32 column tile and a z chunk. Four stages per plane: stash the f (and m) region in LDS; form r~ = r - u
+// on the tile plus halo; the x pass; the y pass into q. Step s runs the
+// stash of plane s, the force of plane s-1, the x pass of plane s-2 and the
+// y pass of plane s-3 against double-buffered LDS, so one barrier per plane
+// separates them and no stage waits for another. Global loads run ahead: the
+// f region of plane s+1 and the per-point data of plane s+1 are requested in
+// step s (the per-point data is consumed in step s+2, hence two register
+// sets and steps taken in pairs).
+constexpr int QTX = 32, QTY = 32;
+
+template <int R, int FM>
+struct PipeLds {
+    static constexpr int W = QTX + 2 * R, PW = (W + 3) & ~3, H = QTY + 2 * R;
+    static constexpr int FW = W + 2, FH = H + 2;
+    static constexpr size_t F_BYTES = (size_t)FH * FW * sizeof(float);
+    static constexpr size_t IN_BYTES = (size_t)3 * H * PW * sizeof(float);
+    static constexpr size_t X_BYTES = (size_t)3 * H * QTX * sizeof(float);
+    static constexpr size_t BYTES = 2 * (F_BYTES * (FM == 2 ? 2 : 1) + IN_BYTES + X_BYTES);
+};
+
+template <int R, int FM>
+__device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bid)
 {
     constexpr bool FORCE = FM > 0, DBL = FM == 2;
-    if (a.stop && *a.stop) return;  // the level has met its stopping rule
-    constexpr int NT = TX * TY;
+    constexpr int NT = QTX * QTY;
     constexpr int K = 2 * R + 1;
-    constexpr int W = TX + 2 * R;
-    constexpr int PW = (W + 3) & ~3;
-    constexpr int H = TY + 2 * R;
-    constexpr int FW = W + 2;  // f region: one more voxel each side for the gradient
-    constexpr int FH = H + 2;
-    constexpr int XITEMS = 3 * H * (TX / SRUN);
-    constexpr int YITEMS = 3 * TX * (TY / SRUN);
-    constexpr int NF = FORCE ? (FH * FW + NT - 1) / NT : 1;  // f-region values per thread
-    constexpr int NP = (H * W + NT - 1) / NT;                // region points per thread
+    using L = PipeLds<R, FM>;
+    constexpr int W = L::W, PW = L::PW, H = L::H, FW = L::FW, FH = L::FH;
+    constexpr int XITEMS = 3 * H * (QTX / SRUN);
+    constexpr int YITEMS = 3 * QTX * (QTY / SRUN);
+    constexpr int NF = FORCE ? (FH * FW + NT - 1) / NT : 1;
+    constexpr int NP = (H * W + NT - 1) / NT;
     static_assert(YITEMS <= NT, "one y item per thread");
+    if (a.stop && *a.stop) return;  // the level has met its stopping rule
 
-    __shared__ __align__(16) float s_in[3][H][PW];
-    __shared__ __align__(16) float s_x[3][H][TX];
-    __shared__ float s_f[FORCE ? FH * FW : 1];
-    __shared__ float s_mm[DBL ? FH * FW : 1];  // m region for grad m (double force)
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* s_f0 = reinterpret_cast<float*>(smem);                                   // [2][FH*FW]
+    float* s_mm0 = s_f0 + (DBL ? 2 * FH * FW : 0);                                  // [2][FH*FW] (DBL)
+    float* s_in0 = reinterpret_cast<float*>(smem + 2 * L::F_BYTES * (DBL ? 2 : 1));  // [2][3][H][PW]
+    float* s_x0 = s_in0 + 2 * 3 * H * PW;                                           // [2][3][H][QTX]
 
     const int lb = xcd_logical_block(bid, a.nblocks);
     const int bx = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
     const int by = rest % a.tiles_y;
     const int bz = rest / a.tiles_y;
-    const int x0 = bx * TX, y0 = by * TY;
+    const int x0 = bx * QTX, y0 = by * QTY;
     const int z0 = bz * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
     const int t = threadIdx.x;
-    const long plane = (long)a.nx * a.ny;
-    const long N = plane * a.nz;
+    // element offsets fit in 32 bits (the ABI bounds N below 2^31)
+    const int plane = a.nx * a.ny;
+    const long N = (long)plane * a.nz;
+    const float* r0p = a.r;
+    const float* r1p = a.r + N;
+    const float* r2p = a.r + 2 * N;
 
-    // Per-thread geometry, fixed over the z loop. Region point q of this
-    // thread sits at clamped voxel (gx, gy); its f neighbours are the
-    // clamped voxels, looked up inside the staged f region.
+    // per-thread geometry, fixed over the sweep. Region point q of this
+    // thread sits at clamped voxel (gx, gy); its f neighbours are the clamped
+    // voxels, looked up inside the staged f region.
     int foff[NF], pofs[NP], pslot[NP], fc_[NP], fxp_[NP], fxm_[NP], fyp_[NP], fym_[NP];
     bool fval[NF], pval[NP], pint[NP];
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
         const int i = t + q * NT;
-        if (FORCE && i < FH * FW) {
+        fval[q] = FORCE && i < FH * FW;
+        if (fval[q]) {
             const int row = i / FW, col = i - row * FW;
             foff[q] = clampi(y0 - R - 1 + row, a.ny) * a.nx + clampi(x0 - R - 1 + col, a.nx);
         } else {
             foff[q] = 0;  // loaded but never stored: keeps the load branch-free
         }
-        fval[q] = FORCE && i < FH * FW;
     }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
@@ -106,24 +128,25 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& a, const int bid)
             fxm_[q] = (gy - byf) * FW + (clampi(gx - 1, a.nx) - bxf);
             fyp_[q] = (clampi(gy + 1, a.ny) - byf) * FW + (gx - bxf);
             fym_[q] = (clampi(gy - 1, a.ny) - byf) * FW + (gx - bxf);
-            pint[q] = row >= R && row < R + TY && col >= R && col < R + TX && x0 - R + col < a.nx &&
+            pint[q] = row >= R && row < R + QTY && col >= R && col < R + QTX && x0 - R + col < a.nx &&
                       y0 - R + row < a.ny;
             pval[q] = true;
         } else {
-            // loaded but never used: keeps the loads branch-free
             pofs[q] = pslot[q] = fc_[q] = fxp_[q] = fxm_[q] = fyp_[q] = fym_[q] = 0;
             pint[q] = false;
             pval[q] = false;
         }
     }
 
-    // prefetch registers for one plane; every load is unconditional (no
-    // divergent branches), so the compiler can keep them in flight across
-    // the barriers of the current plane
-    float pf[NF], pr0[NP], pr1[NP], pr2[NP], pm[NP], pzu[NP], pzd[NP];
-    float pmf[DBL ? NF : 1], pmu[DBL ? NP : 1], pmd[DBL ? NP : 1];
-    auto fetch = [&](int z) {
-        const long zoff = (long)z * plane;
+    const int nplanes = z1 - z0;
+    // registers: the f (and m) region of the next plane; per-point data in two sets
+    float pf[NF], pmf[DBL ? NF : 1];
+    struct Pt {
+        float r0[NP], r1[NP], r2[NP], m[NP], fu[NP], fd[NP], mu[DBL ? NP : 1], md[DBL ? NP : 1];
+    };
+    Pt setA, setB;
+    auto fetch_region = [&](int p) {  // f (and m) region of plane p (clamped: always valid)
+        const int zoff = (z0 + min(p, nplanes - 1)) * plane;
         if (FORCE) {
 #pragma unroll
             for (int q = 0; q < NF; ++q) pf[q] = a.f[zoff + foff[q]];
@@ -132,154 +155,196 @@ __device__ __forceinline__ void plane_body(const PlaneArgs& a, const int bid)
 #pragma unroll
             for (int q = 0; q < NF; ++q) pmf[q] = a.m[zoff + foff[q]];
         }
-        const long zu = (long)clampi(z + 1, a.nz) * plane, zd = (long)clampi(z - 1, a.nz) * plane;
+    };
+    auto fetch_points = [&](Pt& d, int p) {
+        const int z = z0 + min(p, nplanes - 1);
+        const int zoff = z * plane;
+        const int zu = clampi(z + 1, a.nz) * plane, zd = clampi(z - 1, a.nz) * plane;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            pr0[q] = a.r[zoff + pofs[q]];
-            pr1[q] = a.r[N + zoff + pofs[q]];
-            pr2[q] = a.r[2 * N + zoff + pofs[q]];
+            d.r0[q] = r0p[zoff + pofs[q]];
+            d.r1[q] = r1p[zoff + pofs[q]];
+            d.r2[q] = r2p[zoff + pofs[q]];
             if (FORCE) {
-                pm[q] = a.m[zoff + pofs[q]];
-                pzu[q] = a.f[zu + pofs[q]];
-                pzd[q] = a.f[zd + pofs[q]];
+                d.m[q] = a.m[zoff + pofs[q]];
+                d.fu[q] = a.f[zu + pofs[q]];
+                d.fd[q] = a.f[zd + pofs[q]];
             }
             if (DBL) {
-                pmu[q] = a.m[zu + pofs[q]];
-                pmd[q] = a.m[zd + pofs[q]];
+                d.mu[q] = a.m[zu + pofs[q]];
+                d.md[q] = a.m[zd + pofs[q]];
             }
         }
     };
 
-    if (PIPE) fetch(z0 < z1 ? z0 : 0);
-    for (int z = z0; z < z1; ++z) {
-        const long zoff = (long)z * plane;
-        if (!PIPE) fetch(z);
-        float v0[NP], v1[NP], v2[NP], mm[NP], fu[NP], fd[NP], mu_[DBL ? NP : 1], md_[DBL ? NP : 1];
+    // one pipeline step; `par` is s & 1, `cur` holds the point data of plane
+    // s - 1 (consumed here) and receives that of plane s + 1
+    auto step = [&](int s, const int par, Pt& cur) {
+        const int ps = s, pc = s - 1, px = s - 2, py = s - 3;
+        // stash the f (and m) region of plane s, request that of plane s + 1
+        if (FORCE && ps < nplanes) {
+            float* sf = s_f0 + par * (FH * FW);
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            v0[q] = pr0[q];
-            v1[q] = pr1[q];
-            v2[q] = pr2[q];
-            mm[q] = pm[q];
-            fu[q] = pzu[q];
-            fd[q] = pzd[q];
+            for (int q = 0; q < NF; ++q)
+                if (fval[q]) sf[t + q * NT] = pf[q];
             if (DBL) {
-                mu_[q] = pmu[q];
-                md_[q] = pmd[q];
+                float* smm = s_mm0 + par * (FH * FW);
+#pragma unroll
+                for (int q = 0; q < NF; ++q)
+                    if (fval[q]) smm[t + q * NT] = pmf[q];
             }
         }
-        if (FORCE) {
+        fetch_region(ps + 1);
+        // force of plane s - 1 on the tile plus halo: r~ = r - u
+        if (pc >= 0 && pc < nplanes) {
+            const float* sf = s_f0 + (par ^ 1) * (FH * FW);
+            const float* smm = s_mm0 + (par ^ 1) * (FH * FW);
+            float* sin = s_in0 + (par ^ 1) * (3 * H * PW);
+            const int zoff = (z0 + pc) * plane;
 #pragma unroll
-            for (int q = 0; q < NF; ++q)
-                if (fval[q]) s_f[t + q * NT] = pf[q];
-        }
-        if (DBL) {
-#pragma unroll
-            for (int q = 0; q < NF; ++q)
-                if (fval[q]) s_mm[t + q * NT] = pmf[q];
-        }
-        __syncthreads();
-        if (PIPE) fetch(min(z + 1, z1 - 1));
-        // r~ = r - u on the tile plus halo
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            if (!pval[q]) continue;
-            float w0 = v0[q], w1 = v1[q], w2 = v2[q];
-            if (FORCE) {
-                const float fcv = s_f[fc_[q]];
-                const float gxv = (s_f[fxp_[q]] - s_f[fxm_[q]]) * 0.5f;
-                const float gyv = (s_f[fyp_[q]] - s_f[fym_[q]]) * 0.5f;
-                const float gzv = (fu[q] - fd[q]) * 0.5f;
-                const float d = mm[q] - fcv;
-                const float den = gxv * gxv + gyv * gyv + gzv * gzv + d * d;
-                if (den > 0.0f && fabsf(d) >= a.eps_d) {
-                    // den >= d^2 >= eps_d^2 is a normal number: the hardware
-                    // reciprocal (1 ulp) replaces the IEEE division sequence
-                    const float sc = d * __builtin_amdgcn_rcpf(den);
-                    w0 -= sc * gxv;
-                    w1 -= sc * gyv;
-                    w2 -= sc * gzv;
-                }
-                if (DBL) {
-                    // second term of Eq. 1: the same with the gradient of m
-                    const float hx = (s_mm[fxp_[q]] - s_mm[fxm_[q]]) * 0.5f;
-                    const float hy = (s_mm[fyp_[q]] - s_mm[fym_[q]]) * 0.5f;
-                    const float hz = (mu_[q] - md_[q]) * 0.5f;
-                    const float den2 = hx * hx + hy * hy + hz * hz + d * d;
-                    if (den2 > 0.0f && fabsf(d) >= a.eps_d) {
-                        const float sc2 = d * __builtin_amdgcn_rcpf(den2);
-                        w0 -= sc2 * hx;
-                        w1 -= sc2 * hy;
-                        w2 -= sc2 * hz;
+            for (int q = 0; q < NP; ++q) {
+                if (!pval[q]) continue;
+                float w0 = cur.r0[q], w1 = cur.r1[q], w2 = cur.r2[q];
+                if (FORCE) {
+                    const float fcv = sf[fc_[q]];
+                    const float gxv = (sf[fxp_[q]] - sf[fxm_[q]]) * 0.5f;
+                    const float gyv = (sf[fyp_[q]] - sf[fym_[q]]) * 0.5f;
+                    const float gzv = (cur.fu[q] - cur.fd[q]) * 0.5f;
+                    const float d = cur.m[q] - fcv;
+                    const float den = gxv * gxv + gyv * gyv + gzv * gzv + d * d;
+                    if (den > 0.0f && fabsf(d) >= a.eps_d) {
+                        // den >= d^2 >= eps_d^2 is a normal number: the hardware
+                        // reciprocal (1 ulp) replaces the IEEE division sequence
+                        const float sc = d * __builtin_amdgcn_rcpf(den);
+                        w0 -= sc * gxv;
+                        w1 -= sc * gyv;
+                        w2 -= sc * gzv;
+                    }
+                    if (DBL) {
+                        // second term of Eq. 1: the same with the gradient of m
+                        const float hx = (smm[fxp_[q]] - smm[fxm_[q]]) * 0.5f;
+                        const float hy = (smm[fyp_[q]] - smm[fym_[q]]) * 0.5f;
+                        const float hz = (cur.mu[q] - cur.md[q]) * 0.5f;
+                        const float den2 = hx * hx + hy * hy + hz * hz + d * d;
+                        if (den2 > 0.0f && fabsf(d) >= a.eps_d) {
+                            const float sc2 = d * __builtin_amdgcn_rcpf(den2);
+                            w0 -= sc2 * hx;
+                            w1 -= sc2 * hy;
+                            w2 -= sc2 * hz;
+                        }
+                    }
+                    if (a.rt && pint[q]) {
+                        a.rt[zoff + pofs[q]] = w0;
+                        a.rt[N + zoff + pofs[q]] = w1;
+                        a.rt[2 * N + zoff + pofs[q]] = w2;
                     }
                 }
-                if (a.rt && pint[q]) {
-                    a.rt[zoff + pofs[q]] = w0;
-                    a.rt[N + zoff + pofs[q]] = w1;
-                    a.rt[2 * N + zoff + pofs[q]] = w2;
+                sin[pslot[q]] = w0;
+                sin[H * PW + pslot[q]] = w1;
+                sin[2 * H * PW + pslot[q]] = w2;
+            }
+        }
+        fetch_points(cur, ps + 1);
+        // x pass of plane s - 2: 4 consecutive outputs of one row per item
+        if (px >= 0 && px < nplanes) {
+            const float* sin = s_in0 + par * (3 * H * PW);
+            float* sx = s_x0 + par * (3 * H * QTX);
+            for (int i = t; i < XITEMS; i += NT) {
+                const int run = i % (QTX / SRUN), cr = i / (QTX / SRUN);
+                const int c = cr / H, row = cr - c * H;
+                const float* src = sin + (c * H + row) * PW + run * SRUN;
+                float v[(SRUN + 2 * R + 3) & ~3];
+#pragma unroll
+                for (int j = 0; j < (SRUN + 2 * R + 3) / 4; ++j) {
+                    const float4 w4 = *reinterpret_cast<const float4*>(src + 4 * j);
+                    v[4 * j] = w4.x;
+                    v[4 * j + 1] = w4.y;
+                    v[4 * j + 2] = w4.z;
+                    v[4 * j + 3] = w4.w;
                 }
+                float o[SRUN];
+#pragma unroll
+                for (int rr = 0; rr < SRUN; ++rr) {
+                    float sacc = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[rr + j], sacc);
+                    o[rr] = sacc;
+                }
+                *reinterpret_cast<float4*>(sx + (c * H + row) * QTX + run * SRUN) = make_float4(o[0], o[1], o[2], o[3]);
             }
-            (&s_in[0][0][0])[pslot[q]] = w0;
-            (&s_in[1][0][0])[pslot[q]] = w1;
-            (&s_in[2][0][0])[pslot[q]] = w2;
         }
-        __syncthreads();
-        // x pass: 4 consecutive outputs of one row per item
-        for (int i = t; i < XITEMS; i += NT) {
-            const int run = i % (TX / SRUN), cr = i / (TX / SRUN);
-            const int c = cr / H, row = cr - c * H;
-            const float* src = &s_in[c][row][run * SRUN];
-            float v[(SRUN + 2 * R + 3) & ~3];
-#pragma unroll
-            for (int j = 0; j < (SRUN + 2 * R + 3) / 4; ++j) {
-                const float4 w4 = *reinterpret_cast<const float4*>(src + 4 * j);
-                v[4 * j] = w4.x;
-                v[4 * j + 1] = w4.y;
-                v[4 * j + 2] = w4.z;
-                v[4 * j + 3] = w4.w;
-            }
-            float o[SRUN];
-#pragma unroll
-            for (int rr = 0; rr < SRUN; ++rr) {
-                float sacc = 0.0f;
-#pragma unroll
-                for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[rr + j], sacc);
-                o[rr] = sacc;
-            }
-            *reinterpret_cast<float4*>(&s_x[c][row][run * SRUN]) = make_float4(o[0], o[1], o[2], o[3]);
-        }
-        __syncthreads();
-        // y pass: 4 consecutive outputs of one column per item, written to q
-        if (t < YITEMS) {
-            const int col = t % TX, cr = t / TX;
-            const int run = cr % (TY / SRUN), c = cr / (TY / SRUN);
+        // y pass of plane s - 3: 4 consecutive outputs of one column per item, to q
+        if (py >= 0 && py < nplanes && t < YITEMS) {
+            const float* sx = s_x0 + (par ^ 1) * (3 * H * QTX);
+            const int col = t % QTX, cr = t / QTX;
+            const int run = cr % (QTY / SRUN), c = cr / (QTY / SRUN);
             float v[SRUN + 2 * R];
 #pragma unroll
-            for (int j = 0; j < SRUN + 2 * R; ++j) v[j] = s_x[c][run * SRUN + j][col];
+            for (int j = 0; j < SRUN + 2 * R; ++j) v[j] = sx[(c * H + run * SRUN + j) * QTX + col];
             const int ox = x0 + col;
+            float* qc = a.q + c * N;
+            const int zoff = (z0 + py) * plane;
 #pragma unroll
             for (int rr = 0; rr < SRUN; ++rr) {
                 float sacc = 0.0f;
 #pragma unroll
                 for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[rr + j], sacc);
                 const int oy = y0 + run * SRUN + rr;
-                if (ox < a.nx && oy < a.ny) a.q[c * N + zoff + (long)oy * a.nx + ox] = sacc;
+                if (ox < a.nx && oy < a.ny) qc[zoff + oy * a.nx + ox] = sacc;
             }
         }
+        __syncthreads();
+    };
+
+    fetch_region(0);
+    fetch_points(setB, 0);  // plane 0's point data, consumed in step 1 (odd)
+    const int nsteps = nplanes + 3;
+    for (int s = 0; s < nsteps; s += 2) {
+        // even steps consume plane s - 1 (odd) from setA and refill it with plane s + 1
+        step(s, 0, setA);
+        if (s + 1 < nsteps) step(s + 1, 1, setB);
     }
 }
 
-template <int R, int FM, int TX, int TY, bool PIPE>
-__global__ __launch_bounds__(TX* TY) void k_plane_xy(PlaneArgs a)
+template <int R, int FM>
+__global__ __launch_bounds__(QTX* QTY) void k_plane_pipe(PlaneArgs a)
 {
-    plane_body<R, FM, TX, TY, PIPE>(a, blockIdx.x);
+    plane_pipe_body<R, FM>(a, blockIdx.x);
 }
 
-template <int R, int FM, int TX, int TY, bool PIPE>
-__global__ __launch_bounds__(TX* TY) void k_plane_xy_batch(Batch<PlaneArgs> b)
+template <int R, int FM>
+__global__ __launch_bounds__(QTX* QTY) void k_plane_pipe_batch(Batch<PlaneArgs> b)
 {
     const int v = batch_volume(b.start, b.n, blockIdx.x);
-    plane_body<R, FM, TX, TY, PIPE>(b.v[v], blockIdx.x - b.start[v]);
+    plane_pipe_body<R, FM>(b.v[v], blockIdx.x - b.start[v]);
+}
+
+// Raises the dynamic LDS limit of a kernel once (first launch).
+template <class F>
+void lds_attr_once(F* kernel, size_t bytes, bool& done)
+{
+    if (!done && bytes > 65536) {
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        done = true;
+    }
+}
+
+template <int R, int FM>
+void launch_pipe_one(const PlaneArgs& a, hipStream_t st)
+{
+    constexpr size_t lds = PipeLds<R, FM>::BYTES;
+    static bool done = false;
+    lds_attr_once(k_plane_pipe<R, FM>, lds, done);
+    hipLaunchKernelGGL((k_plane_pipe<R, FM>), dim3(a.nblocks), dim3(QTX * QTY), lds, st, a);
+}
+
+template <int R, int FM>
+void launch_pipe_batch_one(const Batch<PlaneArgs>& b, hipStream_t st)
+{
+    constexpr size_t lds = PipeLds<R, FM>::BYTES;
+    static bool done = false;
+    lds_attr_once(k_plane_pipe_batch<R, FM>, lds, done);
+    hipLaunchKernelGGL((k_plane_pipe_batch<R, FM>), dim3(b.start[b.n]), dim3(QTX * QTY), lds, st, b);
 }
 
 struct ZArgs {
@@ -307,22 +372,31 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
 {
     constexpr int K = 2 * R + 1;
     if (a.stop && *a.stop) return;  // the level has met its stopping rule
-    const long col0 = (long)(bid % a.colblocks) * ZNT + threadIdx.x;
-    if (!NORM && col0 >= a.ncols) return;
-    const bool act = col0 < a.ncols;
-    const long col = act ? col0 : a.ncols - 1;  // idle lanes (NORM) read a valid column
+    // element offsets fit in 32 bits (the ABI bounds N below 2^31); the three
+    // field components get their own base pointers
+    const int col0 = (bid % a.colblocks) * ZNT + (int)threadIdx.x;
+    if (!NORM && col0 >= (int)a.ncols) return;
+    const bool act = col0 < (int)a.ncols;
+    const int col = act ? col0 : (int)a.ncols - 1;  // idle lanes (NORM) read a valid column
+    const int xcol = col % a.nx, ycol = col / a.nx;
     const int z0 = (bid / a.colblocks) * a.zchunk;
     const int z1 = min(a.nz, z0 + a.zchunk);
-    const long plane = (long)a.nx * a.ny;
-    const long N = plane * a.nz;
+    const int plane = a.nx * a.ny;
+    const long N = (long)plane * a.nz;
+    const float* q0 = a.q;
+    const float* q1 = a.q + N;
+    const float* q2 = a.q + 2 * N;
+    float* o0 = a.out;
+    float* o1 = a.out + N;
+    float* o2 = a.out + 2 * N;
     float ring[3][K];
     float n1[3], n2[3];  // the next two planes, loads in flight
     double s_dr = 0.0, s_r = 0.0;
     auto load = [&](int p, float* dst) {
-        const long o = (long)clampi(z0 - R + p, a.nz) * plane + col;
-        dst[0] = a.q[o];
-        dst[1] = a.q[N + o];
-        dst[2] = a.q[2 * N + o];
+        const int o = clampi(z0 - R + p, a.nz) * plane + col;
+        dst[0] = q0[o];
+        dst[1] = q1[o];
+        dst[2] = q2[o];
     };
     const int nplanes = (z1 - z0) + 2 * R;
     load(0, n1);
@@ -340,7 +414,8 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
             }
             load(p + 2, n2);  // past the chunk end this re-reads a clamped plane
             if (p >= K - 1) {
-                const long o = (long)(z0 + p - 2 * R) * plane + col;
+                const int oz = z0 + p - 2 * R;
+                const int o = oz * plane + col;
                 float nv[3], ov[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -348,14 +423,17 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
 #pragma unroll
                     for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], ring[c][(k + 1 + j) % K], sacc);
                     nv[c] = sacc;
-                    if (NORM) ov[c] = a.out[c * N + o];
+                }
+                if (NORM) {
+                    ov[0] = o0[o];
+                    ov[1] = o1[o];
+                    ov[2] = o2[o];
                 }
                 if (act) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) a.out[c * N + o] = nv[c];
-                    if (WARP)
-                        a.m[o] = warp_at(a.ct, (int)(col % a.nx), (int)(col / a.nx), z0 + p - 2 * R, nv[0], nv[1],
-                                         nv[2], a.nx, a.ny, a.nz);
+                    o0[o] = nv[0];
+                    o1[o] = nv[1];
+                    o2[o] = nv[2];
+                    if (WARP) a.m[o] = warp_at(a.ct, xcol, ycol, oz, nv[0], nv[1], nv[2], a.nx, a.ny, a.nz);
                 }
                 if (NORM && act) {
                     const float dx = nv[0] - ov[0], dy = nv[1] - ov[1], dz = nv[2] - ov[2];
@@ -434,18 +512,16 @@ __global__ __launch_bounds__(256) void k_stop_rule(const double* __restrict__ no
     }
 }
 
-// Tile of the xy kernel: 32 x 32 columns, 1024 threads, next plane prefetched.
-constexpr int PTX = 32;
-constexpr int PTY = 32;
-constexpr bool PPIPE = true;
+// Tile of the xy kernel: 32 x 32 columns, 1024 threads.
+constexpr int PTX = QTX;
+constexpr int PTY = QTY;
 
 template <int FM>
 hipError_t launch_plane(const PlaneArgs& a, int R, hipStream_t st)
 {
-    const dim3 g(a.nblocks);
     switch (R) {
 #define DISC_R(RR) \
-    case RR: hipLaunchKernelGGL((k_plane_xy<RR, FM, PTX, PTY, PPIPE>), g, dim3(PTX * PTY), 0, st, a); break;
+    case RR: launch_pipe_one<RR, FM>(a, st); break;
         DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
 #undef DISC_R
         default: return hipErrorInvalidValue;
@@ -599,14 +675,13 @@ hipError_t launch_force_xy_batch(const BatchVol* vols, int n, float eps_d, int f
         a.eps_d = eps_d;
         b.start[v + 1] = b.start[v] + a.nblocks;
     }
-    const dim3 g((unsigned)b.start[n]);
     switch (t.R) {
-#define DISC_R(RR)                                                                                       \
-    case RR:                                                                                             \
-        if (force_mode == 1)                                                                             \
-            hipLaunchKernelGGL((k_plane_xy_batch<RR, 2, PTX, PTY, PPIPE>), g, dim3(PTX * PTY), 0, st, b); \
-        else                                                                                             \
-            hipLaunchKernelGGL((k_plane_xy_batch<RR, 1, PTX, PTY, PPIPE>), g, dim3(PTX * PTY), 0, st, b); \
+#define DISC_R(RR)                           \
+    case RR:                                 \
+        if (force_mode == 1)                 \
+            launch_pipe_batch_one<RR, 2>(b, st); \
+        else                                 \
+            launch_pipe_batch_one<RR, 1>(b, st); \
         break;
         DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
 #undef DISC_R
