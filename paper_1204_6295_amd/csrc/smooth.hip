@@ -477,6 +477,43 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z_batch(Batch<ZArgs> b)
     smooth_z_body<R, false, false>(b.v[v], blockIdx.x - b.start[v]);
 }
 
+// One output voxel per thread (small volumes, where the chunk planner gives
+// one-plane chunks): the 2R + 1 planes of its column are requested at once,
+// instead of streaming them through the ring with two planes in flight.
+template <int R, bool WARP>
+__global__ __launch_bounds__(ZNT) void k_smooth_z_direct(ZArgs a)
+{
+    constexpr int K = 2 * R + 1;
+    if (a.stop && *a.stop) return;  // the level has met its stopping rule
+    const int col = (blockIdx.x % a.colblocks) * ZNT + (int)threadIdx.x;
+    const int z = blockIdx.x / a.colblocks;
+    if (col >= (int)a.ncols) return;
+    // element offsets fit in 32 bits (the ABI bounds N below 2^31)
+    const int plane = a.nx * a.ny;
+    const long N = (long)plane * a.nz;
+    float v[3][K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int o = clampi(z - R + j, a.nz) * plane + col;
+        v[0][j] = a.q[o];
+        v[1][j] = a.q[N + o];
+        v[2][j] = a.q[2 * N + o];
+    }
+    float nv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float sacc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[c][j], sacc);
+        nv[c] = sacc;
+    }
+    const int o = z * plane + col;
+    a.out[o] = nv[0];
+    a.out[N + o] = nv[1];
+    a.out[2 * N + o] = nv[2];
+    if (WARP) a.m[o] = warp_at(a.ct, col % a.nx, col / a.nx, z, nv[0], nv[1], nv[2], a.nx, a.ny, a.nz);
+}
+
 // Sec. 2.3 stopping rule after iteration k of a level: l^(k) = sum |dr| /
 // sum |r| from the workgroup partial sums (fixed order), recorded in hist[k];
 // flags[0] := 1 once k >= lag and hist[k - lag] - l^(k) <= eps; flags[1]
@@ -570,6 +607,22 @@ hipError_t launch_z(const float* q, float* out, Dims d, const GaussTaps& t, cons
     a.m = m;
     const bool w = ct && m;
     const dim3 g((unsigned)z_blocks(a));
+    if (!norms && a.zchunk == 1) {
+        // one-plane chunks: every thread requests its whole column window at once
+        switch (t.R) {
+#define DISC_R(RR)                                                                          \
+    case RR:                                                                                \
+        if (w)                                                                              \
+            hipLaunchKernelGGL((k_smooth_z_direct<RR, true>), g, dim3(ZNT), 0, st, a);      \
+        else                                                                                \
+            hipLaunchKernelGGL((k_smooth_z_direct<RR, false>), g, dim3(ZNT), 0, st, a);     \
+        break;
+            DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
+#undef DISC_R
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (t.R) {
 #define DISC_R(RR)                                                                          \
     case RR:                                                                                \
