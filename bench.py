@@ -118,6 +118,33 @@ def backward_rate(disc, ct, cb, r, cfg, plain_ms_per_it, reps=10):
             "vs_plain_iteration": round(ms_grad / plain_ms_per_it, 3)}
 
 
+def variant_rates(disc, ct, cb, cfg, plain_ms, reps=3):
+    """The same registration with the method's variants on: both terms of
+    Eq. 1, the Eq. 7-10 mask and fill, and the Sec. 2.3 stopping rule
+    (iterations actually run per level reported), each against the plain
+    path on the same GPU."""
+    import torch
+
+    base = dict(patch=cfg["patch"], sigma=cfg["sigma"], levels=cfg["levels"], iters=cfg["iters"])
+    out = {}
+    for name, kw in (("double_force", dict(force_mode=1)), ("mask_fill", dict(mask_mode=1)),
+                     ("stopping_rule", dict(stop_eps=1e-4, stop_lag=10))):
+        reg = disc.Registration(**base, **kw)
+
+        def run():
+            reg.set_volumes(ct, cb)
+            reg.run()
+
+        ms = _ms_per_call(run, reps=reps, warm=1)
+        row = {"ms_per_registration": round(ms, 3), "vs_plain": round(ms / plain_ms, 3)}
+        if name == "stopping_rule":
+            row["iterations_run"] = [reg.stats(lv)[0] for lv in range(cfg["levels"])]
+        out[name] = row
+        reg.close()
+        torch.cuda.synchronize()
+    return out
+
+
 def batched_rate(disc, n_pairs=16, iters=100):
     """Batched DISC: n uneven head-and-neck pairs (sizes drawn from
     128^2x64, 192^2x80, 256^2x96, 384^2x128), patch 11^3, sigma 2, one level,
@@ -344,6 +371,10 @@ def main():
         log("differentiable: loss %.3f ms, loss + gradient %.3f ms (%.2fx a plain iteration)" % (
             bwd["ms_loss"], bwd["ms_loss_and_grad"], bwd["vs_plain_iteration"]))
         out["backward"] = bwd
+        var = variant_rates(disc, ct, cb, cfg, ms_per_step)
+        log("variants: " + ", ".join("%s %.2f ms (%.2fx)" % (k, v["ms_per_registration"], v["vs_plain"])
+                                       for k, v in var.items()))
+        out["variants"] = var
         log("batched: generating 16 uneven pairs")
         bat = batched_rate(disc)
         log("batched: sequential %.1f ms, batch eager %.1f ms, batch graph %.1f ms (%.2fx), tiles %s" % (
