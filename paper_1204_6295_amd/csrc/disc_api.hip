@@ -53,7 +53,9 @@ struct disc_ctx {
     float* sd[DISC_MAX_LEVELS] = {};
     float2* ab = nullptr;
     unsigned char* stamp = nullptr;
-    int* left = nullptr;
+    int* filled = nullptr;           // per pass: voxels filled
+    unsigned char* dirty = nullptr;  // per pass and fill tile: filled into
+    size_t dirty_bytes = 0;
     float* consts = nullptr;
     double* dhu = nullptr;
     void* med_scratch = nullptr;
@@ -203,14 +205,18 @@ size_t carve(disc_ctx* c, const disc_params* p, char* base, int L, const Dims* d
         }
         float2* ab = (float2*)cv.take(nf * sizeof(float2));
         unsigned char* stamp = (unsigned char*)cv.take(nf);
-        int* left = (int*)cv.take((size_t)(p->fill_passes + 1) * sizeof(int));
+        int* filled = (int*)cv.take((size_t)(p->fill_passes + 1) * sizeof(int));
+        const size_t dbytes = (disc::fill_dirty_bytes(dims[L - 1], p->fill_passes) + 3) & ~(size_t)3;
+        unsigned char* dirty = (unsigned char*)cv.take(dbytes);
         float* consts = (float*)cv.take(8 * sizeof(float));
         double* dhu = (double*)cv.take(sizeof(double));
         void* med = cv.take(disc::median_scratch_bytes());
         if (c) {
             c->ab = ab;
             c->stamp = stamp;
-            c->left = left;
+            c->filled = filled;
+            c->dirty = dirty;
+            c->dirty_bytes = dbytes;
             c->consts = consts;
             c->dhu = dhu;
             c->med_scratch = med;
@@ -291,7 +297,9 @@ int one_iteration(disc_ctx* c, hipStream_t st)
     if (c->p.mask_mode == 1) {
         {
             Timed tm(c, st, K_CORRECT, l, vox);
-            e = disc::launch_fill(reinterpret_cast<float*>(c->left), c->p.fill_passes + 1, 0.0f, st);
+            e = disc::launch_fill(reinterpret_cast<float*>(c->filled), c->p.fill_passes + 1, 0.0f, st);
+            if (e == hipSuccess)
+                e = disc::launch_fill(reinterpret_cast<float*>(c->dirty), (long)(c->dirty_bytes / 4), 0.0f, st);
             if (e == hipSuccess)
                 e = disc::launch_mask_moments(c->m, c->ys[l], c->s[l], c->sd[l], c->ab, c->stamp, c->consts, d,
                                               c->p.patch, st, flags);
@@ -300,8 +308,8 @@ int one_iteration(disc_ctx* c, hipStream_t st)
         {
             Timed tm(c, st, K_FILL, l, vox);
             for (int pass = 1; pass <= c->p.fill_passes && e == hipSuccess; ++pass)
-                e = disc::launch_fill_pass(c->ab, c->stamp, c->s[l], c->consts, c->left, pass, d, c->p.fill_t,
-                                           flags, st);
+                e = disc::launch_fill_pass(c->ab, c->stamp, c->s[l], c->consts, c->filled, c->dirty, pass, d,
+                                           c->p.fill_t, flags, st);
             if (e == hipSuccess) e = disc::launch_apply_ab(c->ab, c->s[l], c->f, d, flags, st);
         }
         if (e != hipSuccess) return hip_fail(c, e, "fill");

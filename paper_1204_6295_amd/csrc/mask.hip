@@ -11,8 +11,9 @@
 //                        the previous one (no ping-pong copies), and a voxel
 //                        never filled keeps its Eq. 5-6 pair.
 //   apply                I'_s = a S + b.
-// A pass that finds no masked voxel left returns at once (device counter of
-// the previous pass), so no host synchronisation is needed.
+// A pass after one that filled nothing returns at once (device counter of
+// the previous pass), so no host synchronisation is needed; within a pass
+// only the tiles next to the previous pass's fills are visited.
 //
 // Set-up (once per registration): a_m is the exact median of the Eq. 5
 // ratios on the initial images, by a two-pass radix select over the float
@@ -34,19 +35,19 @@ inline dim3 grid_for(Dims d)
     return dim3((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz);
 }
 
-// One fill pass (Eq. 8-10). consts: {hu0, a_lo, a_hi, h}. left[p] counts
-// the voxels still masked after pass p; left[p - 1] == 0 skips the pass.
+// One fill pass (Eq. 8-10). consts: {hu0, a_lo, a_hi, h}. filled[p] counts
+// the voxels pass p filled; filled[p - 1] == 0 (nothing changed) skips the pass.
 __global__ __launch_bounds__(BX* BY) void k_fill_pass(float2* __restrict__ ab, unsigned char* __restrict__ stamp,
                                                       const float* __restrict__ s, const float* __restrict__ consts,
-                                                      int* __restrict__ left, int pass, int nx, int ny, int nz,
+                                                      int* __restrict__ filled, int pass, int nx, int ny, int nz,
                                                       int tx, int ty, int tz, const int* __restrict__ stop)
 {
     if (stop && *stop) return;  // the level has met its stopping rule
-    if (pass > 1 && left[pass - 1] == 0) return;
+    if (pass > 1 && filled[pass - 1] == 0) return;  // the previous pass filled nothing
     const int x = blockIdx.x * BX + threadIdx.x;
     const int y = blockIdx.y * BY + threadIdx.y;
     const int z = blockIdx.z;
-    bool still = false;
+    bool got = false;
     if (x < nx && y < ny) {
         const long i = ((long)z * ny + y) * nx + x;
         if (stamp[i] == 255) {
@@ -73,14 +74,107 @@ __global__ __launch_bounds__(BX* BY) void k_fill_pass(float2* __restrict__ ab, u
             if (sw > 0.0) {
                 ab[i] = make_float2((float)(sa / sw), (float)(sb / sw));
                 stamp[i] = (unsigned char)pass;
-            } else {
-                still = true;
+                got = true;
             }
         }
     }
-    // count the voxels still masked (one atomic per wave that has any)
-    const unsigned long long bal = __ballot(still);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&left[pass], (int)__popcll(bal));
+    // count the voxels filled (one atomic per wave that has any)
+    const unsigned long long bal = __ballot(got);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&filled[pass], (int)__popcll(bal));
+}
+
+// The same pass with the T region staged in LDS: a 32 x 8 tile of one plane
+// loads its region (tile plus the T halo, 2 tz + 1 planes) once as packed
+// {S, a, b, valid}, so the 147-voxel gathers of its masked voxels hit LDS.
+// A tile with no masked voxel returns after one flag test. Neighbours are
+// visited in the same order with the same arithmetic as k_fill_pass, so the
+// results are bitwise the same.
+constexpr int FTX = 32, FTY = 8;
+
+__global__ __launch_bounds__(FTX* FTY) void k_fill_tile(float2* __restrict__ ab, unsigned char* __restrict__ stamp,
+                                                      const float* __restrict__ s, const float* __restrict__ consts,
+                                                      int* __restrict__ filled, unsigned char* __restrict__ dirty,
+                                                      int pass, int nx, int ny, int nz, int tx, int ty, int tz,
+                                                      const int* __restrict__ stop)
+{
+    extern __shared__ __align__(16) float4 reg[];
+    if (stop && *stop) return;  // the level has met its stopping rule
+    // A masked voxel can only succeed if a voxel within its reach was filled
+    // by the previous pass (its T region is unchanged otherwise, and it
+    // failed with that region before): pass p visits only tiles next to a
+    // tile that pass p - 1 filled into, and stops once a pass fills nothing.
+    const int ntx = gridDim.x, nty = gridDim.y;
+    const long ntiles = (long)ntx * nty * nz;
+    const int z = blockIdx.z;
+    if (pass > 1) {
+        if (filled[pass - 1] == 0) return;
+        const unsigned char* prev = dirty + (long)(pass - 1) * ntiles;
+        const int rx = (tx + FTX - 1) / FTX, ry = (ty + FTY - 1) / FTY;
+        bool any = false;
+        for (int dz = max(0, z - tz); dz <= min(nz - 1, z + tz) && !any; ++dz)
+            for (int dy = max(0, (int)blockIdx.y - ry); dy <= min(nty - 1, (int)blockIdx.y + ry) && !any; ++dy)
+                for (int dx = max(0, (int)blockIdx.x - rx); dx <= min(ntx - 1, (int)blockIdx.x + rx); ++dx)
+                    if (prev[((long)dz * nty + dy) * ntx + dx]) {
+                        any = true;
+                        break;
+                    }
+        if (!any) return;
+    }
+    const int lx = threadIdx.x % FTX, ly = threadIdx.x / FTX;
+    const int x = blockIdx.x * FTX + lx, y = blockIdx.y * FTY + ly;
+    const bool inside = x < nx && y < ny;
+    const long i = ((long)z * ny + y) * nx + x;
+    const bool mine = inside && stamp[i] == 255;
+    if (!__syncthreads_or(mine)) return;  // nothing to fill in this tile
+    // stage the region: x0 - tx .. x0 + FTX - 1 + tx, same in y, z - tz .. z + tz
+    const int RW = FTX + 2 * tx, RH = FTY + 2 * ty, RD = 2 * tz + 1;
+    const int rx0 = blockIdx.x * FTX - tx, ry0 = blockIdx.y * FTY - ty, rz0 = z - tz;
+    for (int k = threadIdx.x; k < RW * RH * RD; k += FTX * FTY) {
+        const int cx = k % RW, rest = k / RW;
+        const int cy = rest % RH, cz = rest / RH;
+        const int gx = rx0 + cx, gy = ry0 + cy, gz = rz0 + cz;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // outside the volume: not valid
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
+            const long q = ((long)gz * ny + gy) * nx + gx;
+            if (stamp[q] < pass) {
+                const float2 w = ab[q];
+                v = make_float4(s[q], w.x, w.y, 1.0f);
+            }
+        }
+        reg[k] = v;
+    }
+    __syncthreads();
+    bool got = false;
+    if (mine) {
+        const float h = consts[3];
+        const float inv_h2 = 1.0f / (h * h);
+        const float sx = s[i];
+        double sw = 0.0, sa = 0.0, sb = 0.0;
+        for (int dz = 0; dz < RD; ++dz)
+            for (int dy = 0; dy <= 2 * ty; ++dy) {
+                const float4* row = reg + (dz * RH + ly + dy) * RW + lx;
+                for (int dx = 0; dx <= 2 * tx; ++dx) {
+                    const float4 v = row[dx];
+                    if (v.w == 0.0f) continue;
+                    const float ds = v.x - sx;
+                    const double w = (double)expf(-(ds * ds) * inv_h2);
+                    sw += w;
+                    sa = fma(w, (double)v.y, sa);
+                    sb = fma(w, (double)v.z, sb);
+                }
+            }
+        if (sw > 0.0) {
+            ab[i] = make_float2((float)(sa / sw), (float)(sb / sw));
+            stamp[i] = (unsigned char)pass;
+            got = true;
+        }
+    }
+    // count the voxels filled (one atomic per wave that has any) and mark
+    // the tile for the next pass
+    const unsigned long long bal = __ballot(got);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&filled[pass], (int)__popcll(bal));
+    if (__syncthreads_or(got) && threadIdx.x == 0)
+        dirty[(long)pass * ntiles + ((long)z * nty + blockIdx.y) * ntx + blockIdx.x] = 1;
 }
 
 // I'_s = a S + b.
@@ -212,11 +306,26 @@ __global__ void k_mask_consts(const unsigned* __restrict__ sel, const double* __
 
 }  // namespace
 
-hipError_t launch_fill_pass(float2* ab, unsigned char* stamp, const float* s, const float* consts, int* left,
-                            int pass, Dims d, const int t[3], const int* stop, hipStream_t st)
+size_t fill_dirty_bytes(Dims d, int passes)
 {
-    hipLaunchKernelGGL(k_fill_pass, grid_for(d), dim3(BX, BY), 0, st, ab, stamp, s, consts, left, pass, d.nx, d.ny,
-                       d.nz, t[0] / 2, t[1] / 2, t[2] / 2, stop);
+    const size_t ntiles = (size_t)((d.nx + FTX - 1) / FTX) * ((d.ny + FTY - 1) / FTY) * d.nz;
+    return (size_t)(passes + 1) * ntiles;
+}
+
+hipError_t launch_fill_pass(float2* ab, unsigned char* stamp, const float* s, const float* consts, int* filled,
+                            unsigned char* dirty, int pass, Dims d, const int t[3], const int* stop, hipStream_t st)
+{
+    const int tx = t[0] / 2, ty = t[1] / 2, tz = t[2] / 2;
+    const size_t lds = (size_t)(FTX + 2 * tx) * (FTY + 2 * ty) * (2 * tz + 1) * sizeof(float4);
+    if (lds <= 64 * 1024) {
+        const dim3 g((d.nx + FTX - 1) / FTX, (d.ny + FTY - 1) / FTY, d.nz);
+        hipLaunchKernelGGL(k_fill_tile, g, dim3(FTX * FTY), lds, st, ab, stamp, s, consts, filled, dirty, pass, d.nx,
+                           d.ny, d.nz, tx, ty, tz, stop);
+    } else {
+        // large T regions: gathers straight from cache
+        hipLaunchKernelGGL(k_fill_pass, grid_for(d), dim3(BX, BY), 0, st, ab, stamp, s, consts, filled, pass, d.nx,
+                           d.ny, d.nz, tx, ty, tz, stop);
+    }
     return hipGetLastError();
 }
 
