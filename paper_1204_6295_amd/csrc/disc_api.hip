@@ -54,8 +54,8 @@ struct disc_ctx {
     float2* ab = nullptr;
     unsigned char* stamp = nullptr;
     int* filled = nullptr;           // per pass: voxels filled
-    unsigned char* dirty = nullptr;  // per pass and fill tile: filled into
-    size_t dirty_bytes = 0;
+    disc::FillLists fl{};            // fill work lists
+    long fl_clear = 0;               // floats to zero: queued, then wcount
     float* consts = nullptr;
     double* dhu = nullptr;
     void* med_scratch = nullptr;
@@ -206,8 +206,10 @@ size_t carve(disc_ctx* c, const disc_params* p, char* base, int L, const Dims* d
         float2* ab = (float2*)cv.take(nf * sizeof(float2));
         unsigned char* stamp = (unsigned char*)cv.take(nf);
         int* filled = (int*)cv.take((size_t)(p->fill_passes + 1) * sizeof(int));
-        const size_t dbytes = (disc::fill_dirty_bytes(dims[L - 1], p->fill_passes) + 3) & ~(size_t)3;
-        unsigned char* dirty = (unsigned char*)cv.take(dbytes);
+        // queued and wcount are contiguous: one fill clears both
+        const size_t ntl = (size_t)disc::fill_tiles(dims[L - 1]);
+        int* queued = (int*)cv.take((ntl + (size_t)p->fill_passes + 2) * sizeof(int));
+        int* wl = (int*)cv.take((size_t)(p->fill_passes + 1) * ntl * sizeof(int));
         float* consts = (float*)cv.take(8 * sizeof(float));
         double* dhu = (double*)cv.take(sizeof(double));
         void* med = cv.take(disc::median_scratch_bytes());
@@ -215,8 +217,8 @@ size_t carve(disc_ctx* c, const disc_params* p, char* base, int L, const Dims* d
             c->ab = ab;
             c->stamp = stamp;
             c->filled = filled;
-            c->dirty = dirty;
-            c->dirty_bytes = dbytes;
+            c->fl = disc::FillLists{queued, wl, queued + ntl};
+            c->fl_clear = (long)(ntl + (size_t)p->fill_passes + 2);
             c->consts = consts;
             c->dhu = dhu;
             c->med_scratch = med;
@@ -299,7 +301,7 @@ int one_iteration(disc_ctx* c, hipStream_t st)
             Timed tm(c, st, K_CORRECT, l, vox);
             e = disc::launch_fill(reinterpret_cast<float*>(c->filled), c->p.fill_passes + 1, 0.0f, st);
             if (e == hipSuccess)
-                e = disc::launch_fill(reinterpret_cast<float*>(c->dirty), (long)(c->dirty_bytes / 4), 0.0f, st);
+                e = disc::launch_fill(reinterpret_cast<float*>(c->fl.queued), c->fl_clear, 0.0f, st);
             if (e == hipSuccess)
                 e = disc::launch_mask_moments(c->m, c->ys[l], c->s[l], c->sd[l], c->ab, c->stamp, c->consts, d,
                                               c->p.patch, st, flags);
@@ -307,9 +309,10 @@ int one_iteration(disc_ctx* c, hipStream_t st)
         if (e != hipSuccess) return hip_fail(c, e, "correct (mask)");
         {
             Timed tm(c, st, K_FILL, l, vox);
+            e = disc::launch_fill_seed(c->stamp, c->fl, d, c->p.fill_t, flags, st);
             for (int pass = 1; pass <= c->p.fill_passes && e == hipSuccess; ++pass)
-                e = disc::launch_fill_pass(c->ab, c->stamp, c->s[l], c->consts, c->filled, c->dirty, pass, d,
-                                           c->p.fill_t, flags, st);
+                e = disc::launch_fill_pass(c->ab, c->stamp, c->s[l], c->consts, c->filled, c->fl, pass,
+                                           c->p.fill_passes, d, c->p.fill_t, flags, st);
             if (e == hipSuccess) e = disc::launch_apply_ab(c->ab, c->s[l], c->f, d, flags, st);
         }
         if (e != hipSuccess) return hip_fail(c, e, "fill");

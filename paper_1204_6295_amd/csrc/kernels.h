@@ -89,12 +89,24 @@ hipError_t launch_ssd_finish(const double* partial, int n, double* loss, hipStre
 hipError_t launch_mask_moments(const float* m, const float* ys, const float* s, const float* sd, float2* ab,
                                unsigned char* stamp, const float* consts, Dims d, const int patch[3],
                                hipStream_t st, const int* stop);
-// Fill pass `pass` (1-based) of Eq. 8-10 over the T region t[3]; filled[pass]
-// counts the voxels it filled and dirty[pass] marks the tiles it filled into
-// (filled and dirty, fill_dirty_bytes(d, passes) bytes, zeroed per iteration).
-size_t fill_dirty_bytes(Dims d, int passes);
+// Work lists of the Eq. 8-10 fill passes: queued[fill_tiles(d)] and
+// wcount[passes + 2] zeroed per iteration, wl[(passes + 1) * fill_tiles(d)].
+struct FillLists {
+    int* queued;
+    int* wl;
+    int* wcount;
+};
+int fill_tiles(Dims d);
+// Queue the tiles that pass 1 must visit (after the moments sweep has
+// stamped the valid voxels).
+hipError_t launch_fill_seed(const unsigned char* stamp, const FillLists& fl, Dims d, const int t[3],
+                            const int* stop, hipStream_t st);
+// Fill pass `pass` (1-based, of `passes`) of Eq. 8-10 over the T region t[3].
+// filled[pass] counts the voxels it filled where the region is too large for
+// the work-list kernel (filled zeroed per iteration).
 hipError_t launch_fill_pass(float2* ab, unsigned char* stamp, const float* s, const float* consts, int* filled,
-                            unsigned char* dirty, int pass, Dims d, const int t[3], const int* stop, hipStream_t st);
+                            const FillLists& fl, int pass, int passes, Dims d, const int t[3], const int* stop,
+                            hipStream_t st);
 // f = a S + b.
 hipError_t launch_apply_ab(const float2* ab, const float* s, float* f, Dims d, const int* stop, hipStream_t st);
 // Set-up: a = STD(CT)/STD(S) per voxel (-1 where a patch is flat), then the

@@ -11,14 +11,16 @@
 //                        the previous one (no ping-pong copies), and a voxel
 //                        never filled keeps its Eq. 5-6 pair.
 //   apply                I'_s = a S + b.
-// A pass after one that filled nothing returns at once (device counter of
-// the previous pass), so no host synchronisation is needed; within a pass
-// only the tiles next to the previous pass's fills are visited.
+// A pass visits only the tiles queued for it by the previous pass (or by the
+// seed), and in them evaluates only the masked voxels within reach of a
+// voxel the previous pass filled; device-side queues need no host
+// synchronisation.
 //
 // Set-up (once per registration): a_m is the exact median of the Eq. 5
 // ratios on the initial images, by a two-pass radix select over the float
 // bit patterns (non-negative floats order like their bits): 16-bit digit
 // histograms with atomics, then a one-workgroup scan per digit.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -29,6 +31,7 @@ namespace {
 
 constexpr int BX = 64;
 constexpr int BY = 4;
+constexpr float kLog2e = 1.44269504088896341f;
 
 inline dim3 grid_for(Dims d)
 {
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(BX* BY) void k_fill_pass(float2* __restrict__ ab, u
         const long i = ((long)z * ny + y) * nx + x;
         if (stamp[i] == 255) {
             const float h = consts[3];
-            const float inv_h2 = 1.0f / (h * h);
+            const float kw = kLog2e / (h * h);  // Eq. 10 weight as a power of 2
             const float sx = s[i];
             double sw = 0.0, sa = 0.0, sb = 0.0;
             const int z0 = max(0, z - tz), z1 = min(nz - 1, z + tz);
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(BX* BY) void k_fill_pass(float2* __restrict__ ab, u
                     for (int xx = x0; xx <= x1; ++xx) {
                         if (stamp[row + xx] >= pass) continue;
                         const float ds = s[row + xx] - sx;
-                        const double w = (double)expf(-(ds * ds) * inv_h2);
+                        const double w = (double)exp2f(-(ds * ds) * kw);
                         const float2 v = ab[row + xx];
                         sw += w;
                         sa = fma(w, (double)v.x, sa);
@@ -83,98 +86,228 @@ __global__ __launch_bounds__(BX* BY) void k_fill_pass(float2* __restrict__ ab, u
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&filled[pass], (int)__popcll(bal));
 }
 
-// The same pass with the T region staged in LDS: a 32 x 8 tile of one plane
-// loads its region (tile plus the T halo, 2 tz + 1 planes) once as packed
-// {S, a, b, valid}, so the 147-voxel gathers of its masked voxels hit LDS.
-// A tile with no masked voxel returns after one flag test. Neighbours are
-// visited in the same order with the same arithmetic as k_fill_pass, so the
-// results are bitwise the same.
-constexpr int FTX = 32, FTY = 8;
+// The same pass driven by work lists, with the T region staged in LDS; one
+// 32 x 8 tile of one plane at a time per workgroup. Few masked voxels can
+// change in a pass: one whose T region holds no voxel filled by the previous
+// pass (for pass 1: no valid voxel) has the valid set it already failed
+// with, so it fails again. Hence
+//   seed     every tile with a valid voxel queues, for pass 1, the tiles
+//            within reach of its valid voxels
+//   pass p   visits only the tiles queued for p: stages the region's stamps
+//            (tile plus the T halo, 2 tz + 1 planes; one region row per
+//            wave, four rows per round trip), ORs "filled by pass p - 1"
+//            (pass 1: valid) along z and then over the x-y window, lists the
+//            masked voxels that see such a voxel, and only if there are any
+//            stages {S, a, b, valid} and evaluates them, one per thread;
+//            tiles that fill something queue, for p + 1, the tiles within
+//            reach of what they filled
+// Listed voxels visit their neighbours in the same order with the same
+// arithmetic as k_fill_pass, so the results are bitwise the same.
+// Queues: queued[tile] = last pass the tile was queued for (an atomicMax
+// admits each tile once per pass), wl[p * ntiles ...] the tiles of pass p,
+// wcount[p] their number; queued and wcount start at zero every iteration.
+constexpr int FTX = 32, FTY = 8, FW = FTX * FTY / 64;  // FW waves per tile
 
-__global__ __launch_bounds__(FTX* FTY) void k_fill_tile(float2* __restrict__ ab, unsigned char* __restrict__ stamp,
+struct FillQ {
+    int* queued;
+    int* wl;
+    int* wcount;
+    int ntx, nty, nz;
+    int tx, ty, tz;
+};
+
+// Queue for pass `to` every tile that holds a voxel within the T reach of a
+// voxel of tile (bx, by, z) with src set. Block-wide; bb: 4 ints of LDS.
+__device__ void queue_reach(const FillQ& q, bool src, int to, int bx, int by, int z, int* bb)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        bb[0] = FTX;
+        bb[1] = -1;
+        bb[2] = FTY;
+        bb[3] = -1;
+    }
+    const unsigned long long m = __ballot(src);
+    __syncthreads();
+    if (lane == 0 && m) {
+        // a wave holds rows 2 wave and 2 wave + 1 of the tile, 32 voxels each
+        const unsigned cols = (unsigned)m | (unsigned)(m >> 32);
+        atomicMin(&bb[0], __ffs(cols) - 1);
+        atomicMax(&bb[1], 31 - __clz(cols));
+        atomicMin(&bb[2], 2 * wave + ((unsigned)m ? 0 : 1));
+        atomicMax(&bb[3], 2 * wave + ((m >> 32) ? 1 : 0));
+    }
+    __syncthreads();
+    if (bb[1] < 0) return;  // uniform: nothing to spread
+    const int X0 = max(0, (bx * FTX + bb[0] - q.tx) / FTX), X1 = min(q.ntx - 1, (bx * FTX + bb[1] + q.tx) / FTX);
+    const int Y0 = max(0, (by * FTY + bb[2] - q.ty) / FTY), Y1 = min(q.nty - 1, (by * FTY + bb[3] + q.ty) / FTY);
+    const int Z0 = max(0, z - q.tz), Z1 = min(q.nz - 1, z + q.tz);
+    const int cx = X1 - X0 + 1, cy = Y1 - Y0 + 1;
+    const int t = threadIdx.x;  // at most 3 x 3 x 15 tiles (tx, ty < 8; tz < 8)
+    if (t < cx * cy * (Z1 - Z0 + 1)) {
+        const int ix = X0 + t % cx, iy = Y0 + (t / cx) % cy, iz = Z0 + t / (cx * cy);
+        const int tile = (iz * q.nty + iy) * q.ntx + ix;
+        if (atomicMax(&q.queued[tile], to) < to) {
+            const long ntiles = (long)q.ntx * q.nty * q.nz;
+            const int slot = atomicAdd(&q.wcount[to], 1);
+            q.wl[(long)to * ntiles + slot] = tile;
+        }
+    }
+}
+
+__global__ __launch_bounds__(FTX* FTY) void k_fill_seed(const unsigned char* __restrict__ stamp, FillQ q, int nx,
+                                                      int ny, const int* __restrict__ stop)
+{
+    __shared__ int bb[4];
+    if (stop && *stop) return;  // the level has met its stopping rule
+    const int x = blockIdx.x * FTX + (int)threadIdx.x % FTX, y = blockIdx.y * FTY + (int)threadIdx.x / FTX;
+    const bool src = x < nx && y < ny && stamp[((long)blockIdx.z * ny + y) * nx + x] == 0;
+    if (!__syncthreads_or(src)) return;
+    queue_reach(q, src, 1, blockIdx.x, blockIdx.y, blockIdx.z, bb);
+}
+
+// CTX, CTY, CTZ: the T half-widths as compile-time constants (0: taken from q)
+template <int CTX, int CTY, int CTZ>
+__global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab, unsigned char* __restrict__ stamp,
                                                       const float* __restrict__ s, const float* __restrict__ consts,
-                                                      int* __restrict__ filled, unsigned char* __restrict__ dirty,
-                                                      int pass, int nx, int ny, int nz, int tx, int ty, int tz,
+                                                      FillQ q, int pass, int passes, int nx, int ny,
                                                       const int* __restrict__ stop)
 {
     extern __shared__ __align__(16) float4 reg[];
+    __shared__ int count;
+    __shared__ int bb[4];
     if (stop && *stop) return;  // the level has met its stopping rule
-    // A masked voxel can only succeed if a voxel within its reach was filled
-    // by the previous pass (its T region is unchanged otherwise, and it
-    // failed with that region before): pass p visits only tiles next to a
-    // tile that pass p - 1 filled into, and stops once a pass fills nothing.
-    const int ntx = gridDim.x, nty = gridDim.y;
-    const long ntiles = (long)ntx * nty * nz;
-    const int z = blockIdx.z;
-    if (pass > 1) {
-        if (filled[pass - 1] == 0) return;
-        const unsigned char* prev = dirty + (long)(pass - 1) * ntiles;
-        const int rx = (tx + FTX - 1) / FTX, ry = (ty + FTY - 1) / FTY;
-        bool any = false;
-        for (int dz = max(0, z - tz); dz <= min(nz - 1, z + tz) && !any; ++dz)
-            for (int dy = max(0, (int)blockIdx.y - ry); dy <= min(nty - 1, (int)blockIdx.y + ry) && !any; ++dy)
-                for (int dx = max(0, (int)blockIdx.x - rx); dx <= min(ntx - 1, (int)blockIdx.x + rx); ++dx)
-                    if (prev[((long)dz * nty + dy) * ntx + dx]) {
-                        any = true;
-                        break;
-                    }
-        if (!any) return;
-    }
-    const int lx = threadIdx.x % FTX, ly = threadIdx.x / FTX;
-    const int x = blockIdx.x * FTX + lx, y = blockIdx.y * FTY + ly;
-    const bool inside = x < nx && y < ny;
-    const long i = ((long)z * ny + y) * nx + x;
-    const bool mine = inside && stamp[i] == 255;
-    if (!__syncthreads_or(mine)) return;  // nothing to fill in this tile
-    // stage the region: x0 - tx .. x0 + FTX - 1 + tx, same in y, z - tz .. z + tz
+    const int tx = CTX > 0 ? CTX : q.tx, ty = CTX > 0 ? CTY : q.ty, tz = CTX > 0 ? CTZ : q.tz, nz = q.nz;
+    // region rows a wave loads per round trip: all of them for fixed T
+    constexpr int NB = CTX > 0 ? ((FTY + 2 * CTY) * (2 * CTZ + 1) + FW - 1) / FW : 4;
+    const long ntiles = (long)q.ntx * q.nty * nz;
+    const int ntodo = q.wcount[pass];
+    // LDS: {S, a, b, valid} per region voxel, the region's stamps (255
+    // outside the volume), the z-OR of "filled by pass p - 1" per region
+    // column, and the list of voxels to evaluate
     const int RW = FTX + 2 * tx, RH = FTY + 2 * ty, RD = 2 * tz + 1;
-    const int rx0 = blockIdx.x * FTX - tx, ry0 = blockIdx.y * FTY - ty, rz0 = z - tz;
-    for (int k = threadIdx.x; k < RW * RH * RD; k += FTX * FTY) {
-        const int cx = k % RW, rest = k / RW;
-        const int cy = rest % RH, cz = rest / RH;
-        const int gx = rx0 + cx, gy = ry0 + cy, gz = rz0 + cz;
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // outside the volume: not valid
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
-            const long q = ((long)gz * ny + gy) * nx + gx;
-            if (stamp[q] < pass) {
-                const float2 w = ab[q];
-                v = make_float4(s[q], w.x, w.y, 1.0f);
+    const int plane = RW * RH, nreg = plane * RD, rows = RH * RD;
+    unsigned char* rst = reinterpret_cast<unsigned char*>(reg + nreg);
+    unsigned char* zany = rst + nreg;
+    int* list = reinterpret_cast<int*>(rst + ((nreg + plane + 3) & ~3));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = threadIdx.x % FTX, ly = threadIdx.x / FTX;
+    const unsigned char fresh = (unsigned char)(pass - 1);  // pass 1: the valid voxels (stamp 0)
+    const float h = consts[3];
+    const float kw = kLog2e / (h * h);  // Eq. 10 weight as a power of 2
+    for (int e = blockIdx.x; e < ntodo; e += gridDim.x) {
+        const int tile = q.wl[(long)pass * ntiles + e];
+        const int bx = tile % q.ntx, by = (tile / q.ntx) % q.nty, z = tile / (q.ntx * q.nty);
+        const int x0 = bx * FTX, y0 = by * FTY;
+        const int rx0 = x0 - tx, ry0 = y0 - ty, rz0 = z - tz;
+        const int gx = rx0 + lane;
+        const bool xin = lane < RW && gx >= 0 && gx < nx;  // RW <= 46 lanes
+        __syncthreads();  // the previous tile is done with LDS
+        for (int r0 = wave; r0 < rows; r0 += NB * FW) {
+            unsigned char v[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int r = r0 + j * FW;  // wave-uniform
+                const int gy = ry0 + r % RH, gz = rz0 + r / RH;
+                v[j] = 255;
+                if (r < rows && xin && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+                    v[j] = stamp[((long)gz * ny + gy) * nx + gx];
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (r0 + j * FW < rows && lane < RW) rst[(r0 + j * FW) * RW + lane] = v[j];
+        }
+        if (threadIdx.x == 0) count = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < plane; k += FTX * FTY) {
+            unsigned char o = 0;
+            for (int dz = 0; dz < RD; ++dz) o |= rst[dz * plane + k] == fresh;
+            zany[k] = o;
+        }
+        __syncthreads();
+        const bool inside = x0 + lx < nx && y0 + ly < ny;
+        const bool mine = inside && rst[(tz * RH + ly + ty) * RW + lx + tx] == 255;
+        bool need = false;
+        if (mine) {
+            for (int dy = 0; dy <= 2 * ty && !need; ++dy) {
+                const unsigned char* row = zany + (ly + dy) * RW + lx;
+                for (int dx = 0; dx <= 2 * tx; ++dx) need |= row[dx] != 0;
             }
         }
-        reg[k] = v;
-    }
-    __syncthreads();
-    bool got = false;
-    if (mine) {
-        const float h = consts[3];
-        const float inv_h2 = 1.0f / (h * h);
-        const float sx = s[i];
-        double sw = 0.0, sa = 0.0, sb = 0.0;
-        for (int dz = 0; dz < RD; ++dz)
-            for (int dy = 0; dy <= 2 * ty; ++dy) {
-                const float4* row = reg + (dz * RH + ly + dy) * RW + lx;
-                for (int dx = 0; dx <= 2 * tx; ++dx) {
-                    const float4 v = row[dx];
-                    if (v.w == 0.0f) continue;
-                    const float ds = v.x - sx;
-                    const double w = (double)expf(-(ds * ds) * inv_h2);
-                    sw += w;
-                    sa = fma(w, (double)v.y, sa);
-                    sb = fma(w, (double)v.z, sb);
+        const unsigned long long nb = __ballot(need);
+        int base = 0;
+        if (lane == 0 && nb) base = atomicAdd(&count, (int)__popcll(nb));
+        base = __shfl(base, 0);
+        if (need) list[base + __popcll(nb & ((1ull << lane) - 1))] = threadIdx.x;
+        __syncthreads();
+        const int n = count;
+        if (n == 0) continue;  // uniform: no voxel of this tile can change
+        for (int r0 = wave; r0 < rows; r0 += NB * FW) {
+            float sv[NB];
+            float2 w[NB];
+            bool ok[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int r = r0 + j * FW;
+                const int gy = ry0 + r % RH, gz = rz0 + r / RH;
+                // valid stamps only occur inside the volume
+                ok[j] = r < rows && lane < RW && rst[r * RW + lane] < pass;
+                sv[j] = 0.0f;
+                w[j] = make_float2(0.0f, 0.0f);
+                if (ok[j]) {
+                    const long g = ((long)gz * ny + gy) * nx + gx;
+                    sv[j] = s[g];
+                    w[j] = ab[g];
                 }
             }
-        if (sw > 0.0) {
-            ab[i] = make_float2((float)(sa / sw), (float)(sb / sw));
-            stamp[i] = (unsigned char)pass;
-            got = true;
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (r0 + j * FW < rows && lane < RW)
+                    reg[(r0 + j * FW) * RW + lane] = make_float4(sv[j], w[j].x, w[j].y, ok[j] ? 1.0f : 0.0f);
         }
+        __syncthreads();
+        bool got = false;
+        int gl = 0;  // tile-local index of the voxel this thread filled
+        if ((int)threadIdx.x < n) {
+            const int t = list[threadIdx.x];
+            const int vx = t % FTX, vy = t / FTX;
+            const long i = ((long)z * ny + (y0 + vy)) * nx + (x0 + vx);
+            const float sx = s[i];
+            double sw = 0.0, sa = 0.0, sb = 0.0;
+#pragma unroll 1
+            for (int dz = 0; dz < RD; ++dz)
+#pragma unroll 1
+                for (int dy = 0; dy <= 2 * ty; ++dy) {
+                    const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
+                    // branch-free: a voxel that is not valid adds an exact
+                    // zero (its staged S, a, b are 0), so the sums equal
+                    // those over the valid voxels alone
+#pragma unroll
+                    for (int dx = 0; dx <= 2 * tx; ++dx) {
+                        const float4 v = row[dx];
+                        const float ds = v.x - sx;
+                        const float e = exp2f(-(ds * ds) * kw);
+                        const double w = (double)(v.w != 0.0f ? e : 0.0f);
+                        sw += w;
+                        sa = fma(w, (double)v.y, sa);
+                        sb = fma(w, (double)v.z, sb);
+                    }
+                }
+            if (sw > 0.0) {
+                ab[i] = make_float2((float)(sa / sw), (float)(sb / sw));
+                stamp[i] = (unsigned char)pass;
+                got = true;
+                gl = t;
+            }
+        }
+        if (pass == passes || !__syncthreads_or(got)) continue;  // uniform
+        // hand the filled voxels back to their own threads for the reach
+        list[threadIdx.x] = 0;
+        __syncthreads();
+        if (got) list[gl] = 1;
+        __syncthreads();
+        queue_reach(q, list[threadIdx.x] != 0, pass + 1, bx, by, z, bb);
     }
-    // count the voxels filled (one atomic per wave that has any) and mark
-    // the tile for the next pass
-    const unsigned long long bal = __ballot(got);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&filled[pass], (int)__popcll(bal));
-    if (__syncthreads_or(got) && threadIdx.x == 0)
-        dirty[(long)pass * ntiles + ((long)z * nty + blockIdx.y) * ntx + blockIdx.x] = 1;
 }
 
 // I'_s = a S + b.
@@ -306,23 +439,59 @@ __global__ void k_mask_consts(const unsigned* __restrict__ sel, const double* __
 
 }  // namespace
 
-size_t fill_dirty_bytes(Dims d, int passes)
+int fill_tiles(Dims d)
 {
-    const size_t ntiles = (size_t)((d.nx + FTX - 1) / FTX) * ((d.ny + FTY - 1) / FTY) * d.nz;
-    return (size_t)(passes + 1) * ntiles;
+    return ((d.nx + FTX - 1) / FTX) * ((d.ny + FTY - 1) / FTY) * d.nz;
+}
+
+namespace {
+
+// the work-list kernels take a region row per wave (RW <= 64) and one
+// neighbouring tile per thread when queueing
+bool fill_lists_fit(const int t[3], size_t* lds)
+{
+    const int tx = t[0] / 2, ty = t[1] / 2, tz = t[2] / 2;
+    const size_t plane = (size_t)(FTX + 2 * tx) * (FTY + 2 * ty), nreg = plane * (2 * tz + 1);
+    *lds = nreg * sizeof(float4) + ((nreg + plane + 3) & ~(size_t)3) + FTX * FTY * sizeof(int);
+    const int reach = 3 * 3 * (2 * tz + 1);
+    return *lds <= 64 * 1024 && FTX + 2 * tx <= 64 && tx < FTX && ty < FTY && reach <= FTX * FTY;
+}
+
+FillQ make_q(const FillLists& fl, Dims d, const int t[3])
+{
+    return FillQ{fl.queued, fl.wl, fl.wcount, (d.nx + FTX - 1) / FTX, (d.ny + FTY - 1) / FTY, d.nz,
+                 t[0] / 2, t[1] / 2, t[2] / 2};
+}
+
+}  // namespace
+
+hipError_t launch_fill_seed(const unsigned char* stamp, const FillLists& fl, Dims d, const int t[3],
+                            const int* stop, hipStream_t st)
+{
+    size_t lds;
+    if (!fill_lists_fit(t, &lds)) return hipSuccess;  // the cache-gather pass needs no lists
+    const dim3 g((d.nx + FTX - 1) / FTX, (d.ny + FTY - 1) / FTY, d.nz);
+    hipLaunchKernelGGL(k_fill_seed, g, dim3(FTX * FTY), 0, st, stamp, make_q(fl, d, t), d.nx, d.ny, stop);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_pass(float2* ab, unsigned char* stamp, const float* s, const float* consts, int* filled,
-                            unsigned char* dirty, int pass, Dims d, const int t[3], const int* stop, hipStream_t st)
+                            const FillLists& fl, int pass, int passes, Dims d, const int t[3], const int* stop,
+                            hipStream_t st)
 {
-    const int tx = t[0] / 2, ty = t[1] / 2, tz = t[2] / 2;
-    const size_t lds = (size_t)(FTX + 2 * tx) * (FTY + 2 * ty) * (2 * tz + 1) * sizeof(float4);
-    if (lds <= 64 * 1024) {
-        const dim3 g((d.nx + FTX - 1) / FTX, (d.ny + FTY - 1) / FTY, d.nz);
-        hipLaunchKernelGGL(k_fill_tile, g, dim3(FTX * FTY), lds, st, ab, stamp, s, consts, filled, dirty, pass, d.nx,
-                           d.ny, d.nz, tx, ty, tz, stop);
+    size_t lds;
+    if (fill_lists_fit(t, &lds)) {
+        // a grid of at most a few workgroups per CU walks the queued tiles
+        const unsigned grid = (unsigned)std::min(fill_tiles(d), 2048);
+        if (t[0] == 7 && t[1] == 7 && t[2] == 3)  // the 7 x 7 x 3 region of Sec. 2.3
+            hipLaunchKernelGGL((k_fill_list<3, 3, 1>), dim3(grid), dim3(FTX * FTY), lds, st, ab, stamp, s, consts,
+                               make_q(fl, d, t), pass, passes, d.nx, d.ny, stop);
+        else
+            hipLaunchKernelGGL((k_fill_list<0, 0, 0>), dim3(grid), dim3(FTX * FTY), lds, st, ab, stamp, s, consts,
+                               make_q(fl, d, t), pass, passes, d.nx, d.ny, stop);
     } else {
-        // large T regions: gathers straight from cache
+        // large T regions: every masked voxel gathers straight from cache
+        const int tx = t[0] / 2, ty = t[1] / 2, tz = t[2] / 2;
         hipLaunchKernelGGL(k_fill_pass, grid_for(d), dim3(BX, BY), 0, st, ab, stamp, s, consts, filled, pass, d.nx,
                            d.ny, d.nz, tx, ty, tz, stop);
     }

@@ -65,6 +65,43 @@ def test_first_iteration_mask_and_fill(disc):
     assert rel_err(f, f_ref) <= 1e-4
 
 
+@pytest.mark.parametrize("shape,t,passes", [
+    ((48, 48, 48), (3, 3, 1), 10),
+    ((48, 48, 48), (7, 7, 3), 1),
+    ((20, 45, 70), (7, 7, 3), 10),
+    ((20, 45, 70), (5, 9, 5), 4),
+    ((12, 40, 36), (15, 15, 9), 3),  # T region too large for LDS: gathers from cache
+])
+def test_fill_passes_and_regions(disc, shape, t, passes):
+    """One iteration from r = 0 for several T regions and pass counts, on
+    volumes with ragged tiles: the pass structure (which voxels each pass
+    fills, and from what) must equal the oracle's."""
+    from synth.phantom import make_hn_pair
+
+    if shape == (48, 48, 48):
+        ct, cb = _c1()
+    else:
+        # pairs whose |m - S| and a stay at least 1e-4 (relative) from the
+        # thresholds, far beyond FP32 rounding
+        c = make_hn_pair(shape, pair={(20, 45, 70): 0, (12, 40, 36): 3}[shape])
+        ct, cb = c.ct, c.cbct
+    kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(1,), mask_mode=1, fill_t=t, fill_passes=passes)
+    reg = disc.Registration(**kw)
+    reg.set_volumes(to_dev(ct), to_dev(cb))
+    reg.run()
+    f = to_np(reg.corrected())
+    mp = reg.mask_params()
+    _, s = oracle.global_shift(ct, cb)
+    s32 = s.astype(np.float32).astype(np.float64)
+    A, B, xi, used = oracle.mask_fill(ct, s32, (5, 5, 5), 1e-2, mp["hu0"], mp["a_min"], mp["a_max"], mp["h"],
+                                      t=t, passes=passes)
+    f_ref = A * s32 + B
+    print("%s T %s passes %d: masked %.3f, used %d, rel %.3g" % (shape, t, passes, xi.mean(), used,
+                                                                 rel_err(f, f_ref)))
+    assert xi.any() and (~xi).any()
+    assert rel_err(f, f_ref) <= 1e-4
+
+
 def test_masked_registration_matches_oracle(disc):
     ct, cb = _c1()
     kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,), mask_mode=1)
