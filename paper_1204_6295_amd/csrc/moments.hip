@@ -30,7 +30,7 @@ namespace disc {
 
 namespace {
 
-constexpr int RUN = 4;
+constexpr int PRUN = 4;  // outputs per x / y item in the 16 x 16 plane-group kernel
 
 // Epilogue of the sweep: what is made from the patch moments at each voxel.
 // kMask: the Eq. 5-6 pair (a, b) and the Eq. 7 stamp per voxel; kAmed: the
@@ -58,9 +58,9 @@ struct MomArgs {
     double inv_n;
 };
 
-// Window sum over [0, 2r] of src and its squares, then RUN - 1 slides; the
-// RUN results go to dst[0], dst[stride], ...
-template <int RC>
+// Window sum over [0, 2r] of src and its squares, then RN - 1 slides; the
+// RN results go to dst[0], dst[stride], ...
+template <int RC, int RN>
 __device__ inline void window_x(const float* src, int r, double2* dst, int stride)
 {
     const int n = RC >= 0 ? 2 * RC : 2 * r;
@@ -82,7 +82,7 @@ __device__ inline void window_x(const float* src, int r, double2* dst, int strid
     }
     dst[0] = make_double2(u1, u2);
 #pragma unroll
-    for (int k = 1; k < RUN; ++k) {
+    for (int k = 1; k < RN; ++k) {
         const double vi = (double)src[k + n], vo = (double)src[k - 1];
         u1 += vi - vo;
         u2 += fma(vi, vi, -vo * vo);
@@ -95,9 +95,9 @@ template <int RXY, int TS>
 struct MomLds {
     static constexpr int RMAX = RXY >= 0 ? RXY : kMaxPatchRxy;
     static constexpr int MAXH = TS + 2 * RMAX;
-    static constexpr int MAXPW = (TS + 2 * RMAX + 3) & ~3;
+    static constexpr int MAXPW = (TS + 2 * RMAX) | 1;  // odd pitch: the x pass reads rows conflict free
     static constexpr int PXH = MAXH | 1;  // odd pitch: column-major x sums are conflict free
-    static constexpr size_t M_BYTES = (size_t)MAXH * MAXPW * sizeof(float);
+    static constexpr size_t M_BYTES = ((size_t)MAXH * MAXPW * sizeof(float) + 15) & ~(size_t)15;
     static constexpr size_t X_BYTES = (size_t)TS * PXH * sizeof(double2);
     static constexpr size_t Y_BYTES = (size_t)TS * TS * sizeof(double2);
     static constexpr size_t BYTES = 2 * (M_BYTES + X_BYTES + Y_BYTES);
@@ -114,6 +114,7 @@ __device__ __forceinline__ void moments_body(const MomArgs& a, const int bid)
     constexpr int MAXH = L::MAXH, MAXPW = L::MAXPW, PXH = L::PXH;
     constexpr int RZ = PZ / 2;
     constexpr int NQ = (MAXH * MAXPW + NT - 1) / NT;  // region values loaded per thread
+    constexpr int RUN = TS == 32 ? 8 : 4;             // outputs per x / y item
     constexpr int XT = 64 * (TS / RUN);               // x workers: one lane per row, one wave per run
     constexpr int YT = TS * (TS / RUN);               // y workers
     constexpr int YB = (XT + YT <= NT) ? XT : 0;      // y workers follow the x workers if they fit
@@ -199,7 +200,7 @@ __device__ __forceinline__ void moments_body(const MomArgs& a, const int bid)
             // x pass: window [c, c + 2 rx] of the loaded row is the patch row of column c
             const int row = t & 63, run = t >> 6;
             if (row < H)
-                window_x<RXY>(s_m0 + (par ^ 1) * (MAXH * MAXPW) + row * MAXPW + run * RUN, rx,
+                window_x<RXY, RUN>(s_m0 + (par ^ 1) * (MAXH * MAXPW) + row * MAXPW + run * RUN, rx,
                               s_x0 + (par ^ 1) * (TS * PXH) + run * RUN * PXH + row, PXH);
         }
         if (q >= 2 && q - 2 < nplanes && t >= YB && t < YB + YT) {
@@ -361,10 +362,10 @@ constexpr int PG = PTS * PTS;  // threads per plane group
 template <int PZ, int RXY>
 struct PpLds {
     static constexpr int H = PTS + 2 * RXY;
-    static constexpr int PW = (H + 3) & ~3;
+    static constexpr int PW = H | 1;  // odd pitch: the x pass reads rows conflict free
     static constexpr int PXH = H | 1;
     static constexpr int RING = PZ + PPS - 1;
-    static constexpr size_t M_BYTES = (size_t)PPS * H * PW * sizeof(float);
+    static constexpr size_t M_BYTES = ((size_t)PPS * H * PW * sizeof(float) + 15) & ~(size_t)15;
     static constexpr size_t X_BYTES = (size_t)PPS * PTS * PXH * sizeof(double2);
     static constexpr size_t Y_BYTES = (size_t)RING * PG * sizeof(double2);
     static constexpr size_t BYTES = M_BYTES + X_BYTES + Y_BYTES;
@@ -455,17 +456,17 @@ __global__ __launch_bounds__(PPS* PG) void k_moments_pp(MomArgs a)
         __syncthreads();
         // x pass: one item per (row, run of 4 columns)
         if (live) {
-            for (int i = tl; i < H * (PTS / RUN); i += PG) {
+            for (int i = tl; i < H * (PTS / PRUN); i += PG) {
                 const int row = i % H, run = i / H;
-                window_x<RXY>(sm + row * PW + run * RUN, RXY, sx + run * RUN * PXH + row, PXH);
+                window_x<RXY, PRUN>(sm + row * PW + run * PRUN, RXY, sx + run * PRUN * PXH + row, PXH);
             }
         }
         __syncthreads();
         // y pass: one item per (column, run of 4 rows), into the ring slot of plane p
-        if (live && tl < PTS * (PTS / RUN)) {
+        if (live && tl < PTS * (PTS / PRUN)) {
             const int col = tl % PTS, run = tl / PTS;
-            const double2* xs = sx + col * PXH + run * RUN;
-            double2* ys = s_y + (p % RING) * PG + run * RUN * PTS + col;
+            const double2* xs = sx + col * PXH + run * PRUN;
+            double2* ys = s_y + (p % RING) * PG + run * PRUN * PTS + col;
             double u1 = 0.0, u2 = 0.0;
 #pragma unroll
             for (int j = 0; j <= 2 * RXY; ++j) {
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(PPS* PG) void k_moments_pp(MomArgs a)
             }
             ys[0] = make_double2(u1, u2);
 #pragma unroll
-            for (int rr = 1; rr < RUN; ++rr) {
+            for (int rr = 1; rr < PRUN; ++rr) {
                 const double2 vi = xs[rr + 2 * RXY], vo = xs[rr - 1];
                 u1 += vi.x - vo.x;
                 u2 += vi.y - vo.y;
