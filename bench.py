@@ -63,7 +63,7 @@ def measured_traffic(kernel, workload):
     if not (m_b and m_h):
         return None
     h = hashlib.sha256()
-    for rel in ("smooth.hip", "kernels.h"):
+    for rel in ("smooth.hip", "device.h"):
         with open(os.path.join(ROOT, "paper_1204_6295_amd", "csrc", rel), "rb") as fh:
             h.update(fh.read())
     return int(m_b.group(1)) if h.hexdigest() == m_h.group(1) else None
