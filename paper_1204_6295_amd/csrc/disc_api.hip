@@ -865,6 +865,7 @@ struct disc_batch {
     int it = 0;
     bool ready = false;
     bool f_valid = false;
+    bool m_ready = false;  // m holds CT(x + r(x)) for the current field
     std::string err;
     // captured iteration loop: graph_iters iterations, replayed by disc_batch_iterate
     hipStream_t cap = nullptr;
@@ -900,14 +901,19 @@ void drop_graph(disc_batch* b)
     b->graph_iters = 0;
 }
 
+// One iteration of every pair. The z pass also warps the CT with the field
+// it produces, so the standalone warp runs only when m is not yet current
+// (after set-up).
 hipError_t batch_once(disc_batch* b, hipStream_t st)
 {
     const disc::BatchVol* v = b->vols.data();
-    hipError_t e = disc::launch_warp_batch(v, b->n, st);
+    hipError_t e = hipSuccess;
+    if (!b->m_ready) e = disc::launch_warp_batch(v, b->n, st);
     if (e == hipSuccess) e = disc::launch_correct_batch(v, b->n, b->p.patch, b->tiles, st);
     if (e == hipSuccess)
         e = disc::launch_force_xy_batch(v, b->n, b->p.diff_floor, b->p.force_mode, b->taps, b->tiles.plane_target, st);
-    if (e == hipSuccess) e = disc::launch_smooth_z_batch(v, b->n, b->taps, b->tiles.z_target, st);
+    if (e == hipSuccess) e = disc::launch_smooth_z_batch(v, b->n, b->taps, b->tiles.z_target, true, st);
+    if (e == hipSuccess) b->m_ready = true;
     return e;
 }
 
@@ -1033,6 +1039,7 @@ int disc_batch_set_volumes(disc_batch* b, const float* const* ct_dev, const floa
     }
     b->it = 0;
     b->f_valid = false;
+    b->m_ready = false;
     b->ready = true;
     return DISC_OK;
 }
@@ -1049,6 +1056,12 @@ int disc_batch_iterate(disc_batch* b, int n, int use_graph, void* stream)
         for (int k = 0; k < n && e == hipSuccess; ++k) e = batch_once(b, st);
         if (e != hipSuccess) return bfail(b, DISC_EHIP, "batched iteration: %s", hipGetErrorString(e));
     } else {
+        // the captured loop starts from a current m: warp once, eagerly, after set-up
+        if (!b->m_ready) {
+            e = disc::launch_warp_batch(b->vols.data(), b->n, st);
+            if (e != hipSuccess) return bfail(b, DISC_EHIP, "batched warp: %s", hipGetErrorString(e));
+            b->m_ready = true;
+        }
         if (b->graph_iters != n) {
             drop_graph(b);
             if (!b->cap) {

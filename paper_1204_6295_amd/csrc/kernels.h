@@ -132,12 +132,16 @@ struct BatchVol {
     Dims d;
 };
 
-// One DISC iteration of every volume of a batch is these four launches.
+// One DISC iteration of every volume of a batch: the warp (only after set-up;
+// afterwards the z pass of the previous iteration has produced m), the
+// correction, force + xy smoothing, and the z pass.
 hipError_t launch_warp_batch(const BatchVol* vols, int n, hipStream_t st);
 hipError_t launch_correct_batch(const BatchVol* vols, int n, const int patch[3], const BatchTiles& tiles,
                                 hipStream_t st);
 hipError_t launch_force_xy_batch(const BatchVol* vols, int n, float eps_d, int force_mode, const GaussTaps& t,
                                  int target, hipStream_t st);
-hipError_t launch_smooth_z_batch(const BatchVol* vols, int n, const GaussTaps& t, int target, hipStream_t st);
+// warp: also m = CT(x + r(x)) with the new field, the next iteration's warp.
+hipError_t launch_smooth_z_batch(const BatchVol* vols, int n, const GaussTaps& t, int target, bool warp,
+                                 hipStream_t st);
 
 }  // namespace disc

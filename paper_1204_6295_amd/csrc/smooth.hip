@@ -470,11 +470,11 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z(ZArgs a)
     smooth_z_body<R, NORM, WARP>(a, blockIdx.x);
 }
 
-template <int R>
+template <int R, bool WARP>
 __global__ __launch_bounds__(ZNT) void k_smooth_z_batch(Batch<ZArgs> b)
 {
     const int v = batch_volume(b.start, b.n, blockIdx.x);
-    smooth_z_body<R, false, false>(b.v[v], blockIdx.x - b.start[v]);
+    smooth_z_body<R, false, WARP>(b.v[v], blockIdx.x - b.start[v]);
 }
 
 // One output voxel per thread (small volumes, where the chunk planner gives
@@ -743,7 +743,8 @@ hipError_t launch_force_xy_batch(const BatchVol* vols, int n, float eps_d, int f
     return hipGetLastError();
 }
 
-hipError_t launch_smooth_z_batch(const BatchVol* vols, int n, const GaussTaps& t, int target, hipStream_t st)
+hipError_t launch_smooth_z_batch(const BatchVol* vols, int n, const GaussTaps& t, int target, bool warp,
+                                 hipStream_t st)
 {
     if (n < 1 || n > kMaxBatch) return hipErrorInvalidValue;
     Batch<ZArgs> b{};
@@ -751,12 +752,21 @@ hipError_t launch_smooth_z_batch(const BatchVol* vols, int n, const GaussTaps& t
     b.start[0] = 0;
     for (int v = 0; v < n; ++v) {
         b.v[v] = z_args(vols[v].q, vols[v].r, vols[v].d, t, target);
+        if (warp) {
+            b.v[v].ct = vols[v].ct;
+            b.v[v].m = vols[v].m;
+        }
         b.start[v + 1] = b.start[v] + z_blocks(b.v[v]);
     }
     const dim3 g((unsigned)b.start[n]);
     switch (t.R) {
-#define DISC_R(RR) \
-    case RR: hipLaunchKernelGGL(k_smooth_z_batch<RR>, g, dim3(ZNT), 0, st, b); break;
+#define DISC_R(RR)                                                                            \
+    case RR:                                                                                  \
+        if (warp)                                                                             \
+            hipLaunchKernelGGL((k_smooth_z_batch<RR, true>), g, dim3(ZNT), 0, st, b);        \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_smooth_z_batch<RR, false>), g, dim3(ZNT), 0, st, b);       \
+        break;
         DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7) DISC_R(8)
 #undef DISC_R
         default: return hipErrorInvalidValue;
