@@ -33,6 +33,14 @@ constexpr int BX = 64;
 constexpr int BY = 4;
 constexpr float kLog2e = 1.44269504088896341f;
 
+// Eq. 10 weight exp(-dS^2 / h^2) = 2^(-dS^2 kw), kw = log2(e) / h^2, on the
+// hardware base-2 exponential (1 ulp; results below the smallest normal
+// float, |dS| > ~9.4 h, are 0). Shared by both fill kernels.
+__device__ inline float fill_weight(float ds, float kw)
+{
+    return __builtin_amdgcn_exp2f(-(ds * ds) * kw);
+}
+
 inline dim3 grid_for(Dims d)
 {
     return dim3((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz);
@@ -67,7 +75,7 @@ __global__ __launch_bounds__(BX* BY) void k_fill_pass(float2* __restrict__ ab, u
                     for (int xx = x0; xx <= x1; ++xx) {
                         if (stamp[row + xx] >= pass) continue;
                         const float ds = s[row + xx] - sx;
-                        const double w = (double)exp2f(-(ds * ds) * kw);
+                        const double w = (double)fill_weight(ds, kw);
                         const float2 v = ab[row + xx];
                         sw += w;
                         sa = fma(w, (double)v.x, sa);
@@ -101,8 +109,8 @@ __global__ __launch_bounds__(BX* BY) void k_fill_pass(float2* __restrict__ ab, u
 //            stages {S, a, b, valid} and evaluates them, one per thread;
 //            tiles that fill something queue, for p + 1, the tiles within
 //            reach of what they filled
-// Listed voxels visit their neighbours in the same order with the same
-// arithmetic as k_fill_pass, so the results are bitwise the same.
+// Listed voxels see the same neighbours with the same weights as in
+// k_fill_pass; the FP64 sums are grouped by region rows (see below).
 // Queues: queued[tile] = last pass the tile was queued for (an atomicMax
 // admits each tile once per pass), wl[p * ntiles ...] the tiles of pass p,
 // wcount[p] their number; queued and wcount start at zero every iteration.
@@ -176,6 +184,7 @@ __global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab,
     extern __shared__ __align__(16) float4 reg[];
     __shared__ int count;
     __shared__ int bb[4];
+    __shared__ double3 part[FTX * FTY];  // partial sums of the row groups
     if (stop && *stop) return;  // the level has met its stopping rule
     const int tx = CTX > 0 ? CTX : q.tx, ty = CTX > 0 ? CTY : q.ty, tz = CTX > 0 ? CTZ : q.tz, nz = q.nz;
     // region rows a wave loads per round trip: all of them for fixed T
@@ -266,34 +275,52 @@ __global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab,
                     reg[(r0 + j * FW) * RW + lane] = make_float4(sv[j], w[j].x, w[j].y, ok[j] ? 1.0f : 0.0f);
         }
         __syncthreads();
+        // Each listed voxel's T region is split into S groups of region rows
+        // (S <= 3, as many as the workgroup has threads for); a thread sums
+        // one group in FP64, and the voxel's own thread adds the S partial
+        // sums in group order.
+        const int RT = RD * (2 * ty + 1);  // region rows of one voxel
+        const int S = min(3, (FTX * FTY) / n);
+        if ((int)threadIdx.x < n * S) {
+            const int v = (int)threadIdx.x % n, g = (int)threadIdx.x / n;
+            const int t = list[v];
+            const int vx = t % FTX, vy = t / FTX;
+            const float sx = s[((long)z * ny + (y0 + vy)) * nx + (x0 + vx)];
+            double sw = 0.0, sa = 0.0, sb = 0.0;
+#pragma unroll 1
+            for (int r = g * RT / S; r < (g + 1) * RT / S; ++r) {
+                const int dz = r / (2 * ty + 1), dy = r - dz * (2 * ty + 1);
+                const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
+                // branch-free: a voxel that is not valid adds an exact zero
+                // (its staged S, a, b are 0), so the sums equal those over
+                // the valid voxels alone
+#pragma unroll
+                for (int dx = 0; dx <= 2 * tx; ++dx) {
+                    const float4 v4 = row[dx];
+                    const float ds = v4.x - sx;
+                    const float e = fill_weight(ds, kw);
+                    const double w = (double)(v4.w != 0.0f ? e : 0.0f);
+                    sw += w;
+                    sa = fma(w, (double)v4.y, sa);
+                    sb = fma(w, (double)v4.z, sb);
+                }
+            }
+            part[threadIdx.x] = make_double3(sw, sa, sb);
+        }
+        __syncthreads();
         bool got = false;
         int gl = 0;  // tile-local index of the voxel this thread filled
         if ((int)threadIdx.x < n) {
-            const int t = list[threadIdx.x];
-            const int vx = t % FTX, vy = t / FTX;
-            const long i = ((long)z * ny + (y0 + vy)) * nx + (x0 + vx);
-            const float sx = s[i];
             double sw = 0.0, sa = 0.0, sb = 0.0;
-#pragma unroll 1
-            for (int dz = 0; dz < RD; ++dz)
-#pragma unroll 1
-                for (int dy = 0; dy <= 2 * ty; ++dy) {
-                    const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
-                    // branch-free: a voxel that is not valid adds an exact
-                    // zero (its staged S, a, b are 0), so the sums equal
-                    // those over the valid voxels alone
-#pragma unroll
-                    for (int dx = 0; dx <= 2 * tx; ++dx) {
-                        const float4 v = row[dx];
-                        const float ds = v.x - sx;
-                        const float e = exp2f(-(ds * ds) * kw);
-                        const double w = (double)(v.w != 0.0f ? e : 0.0f);
-                        sw += w;
-                        sa = fma(w, (double)v.y, sa);
-                        sb = fma(w, (double)v.z, sb);
-                    }
-                }
+            for (int g = 0; g < S; ++g) {
+                const double3 pg = part[g * n + threadIdx.x];
+                sw += pg.x;
+                sa += pg.y;
+                sb += pg.z;
+            }
             if (sw > 0.0) {
+                const int t = list[threadIdx.x];
+                const long i = ((long)z * ny + (y0 + t / FTX)) * nx + (x0 + t % FTX);
                 ab[i] = make_float2((float)(sa / sw), (float)(sb / sw));
                 stamp[i] = (unsigned char)pass;
                 got = true;
