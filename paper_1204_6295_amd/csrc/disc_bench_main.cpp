@@ -6,7 +6,10 @@
 // and the HIP runtime are used (no Python), so profilers that instrument
 // dispatches see exactly the library's kernels.
 //
-// usage: disc_bench CT.f32 CBCT.f32 NX NY NZ PATCH SIGMA LEVELS ITERS STEPS COPY_MIB
+// usage: disc_bench CT.f32 CBCT.f32 NX NY NZ PATCH SIGMA LEVELS ITERS STEPS COPY_MIB [VARIANT]
+//   VARIANT 0 plain (default), 1 Eq. 7-10 mask and fill (default rules,
+//   T = 7x7x3, 10 passes), 2 both Eq. 1 force terms, 3 the Sec. 2.3 stopping
+//   rule (eps 1e-4, lag 10).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -45,19 +48,21 @@ static bool read_raw(const char* path, std::vector<float>& v)
 
 int main(int argc, char** argv)
 {
-    if (argc != 12) {
+    if (argc != 12 && argc != 13) {
         std::fprintf(stderr,
-                     "usage: %s CT.f32 CBCT.f32 NX NY NZ PATCH SIGMA LEVELS ITERS STEPS COPY_MIB\n",
+                     "usage: %s CT.f32 CBCT.f32 NX NY NZ PATCH SIGMA LEVELS ITERS STEPS COPY_MIB [VARIANT]\n",
                      argv[0]);
         return 2;
     }
+    const int variant = argc == 13 ? std::atoi(argv[12]) : 0;
     const int nx = std::atoi(argv[3]), ny = std::atoi(argv[4]), nz = std::atoi(argv[5]);
     const int patch = std::atoi(argv[6]);
     const float sigma = (float)std::atof(argv[7]);
     const int levels = std::atoi(argv[8]), iters = std::atoi(argv[9]);
     const int steps = std::atoi(argv[10]);
     const size_t copy_bytes = (size_t)std::atol(argv[11]) << 20;
-    if (nx < 1 || ny < 1 || nz < 1 || levels < 1 || levels > DISC_MAX_LEVELS || steps < 0) {
+    if (nx < 1 || ny < 1 || nz < 1 || levels < 1 || levels > DISC_MAX_LEVELS || steps < 0 || variant < 0 ||
+        variant > 3) {
         std::fprintf(stderr, "invalid sizes\n");
         return 2;
     }
@@ -74,6 +79,12 @@ int main(int argc, char** argv)
     p.sigma = sigma;
     p.levels = levels;
     for (int l = 0; l < DISC_MAX_LEVELS; ++l) p.iters[l] = l < levels ? iters : 0;
+    if (variant == 1) p.mask_mode = 1;
+    if (variant == 2) p.force_mode = 1;
+    if (variant == 3) {
+        p.stop_eps = 1e-4f;
+        p.stop_lag = 10;
+    }
     disc_ctx* c = nullptr;
     CHECK_DISC(nullptr, disc_create(&p, &c));
     const size_t ws_bytes = disc_workspace_bytes(&p, nx, ny, nz);
