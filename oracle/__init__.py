@@ -20,6 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "disc_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+_HDR = os.path.join(_HERE, "disc_oracle.h")
 
 _D = ctypes.POINTER(ctypes.c_double)
 _F = ctypes.POINTER(ctypes.c_float)
@@ -93,7 +94,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        # build when missing or older than the C source
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(_SRC), os.path.getmtime(_HDR)):
             build()
         L = ctypes.CDLL(_SO)
         L.orc_threads.restype = ctypes.c_int

@@ -334,6 +334,21 @@ int orc_fill(const double* a0, const double* b0, const unsigned char* valid0, co
                     nB[i] = B[i];
                     nvalid[i] = valid[i];
                     if (valid[i]) continue;
+                    /* Eq. 9 is a ratio of sums of the Eq. 10 weights, all of which
+                     * are positive: dividing every weight by the largest one
+                     * (smallest dS^2) leaves it unchanged and keeps it away from
+                     * underflow, so any voxel with a valid neighbour is filled */
+                    double d2min = INFINITY;
+                    for (int k = -tz; k <= tz; ++k)
+                        for (int jj = -ty; jj <= ty; ++jj)
+                            for (int ii = -tx; ii <= tx; ++ii) {
+                                int xx = x + ii, yy = y + jj, zz = z + k;
+                                if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+                                long q = lin(xx, yy, zz, nx, ny);
+                                if (!valid[q]) continue;
+                                double ds = s[q] - s[i];
+                                if (ds * ds < d2min) d2min = ds * ds;
+                            }
                     double sw = 0.0, sa = 0.0, sb = 0.0;
                     for (int k = -tz; k <= tz; ++k)
                         for (int jj = -ty; jj <= ty; ++jj)
@@ -343,7 +358,7 @@ int orc_fill(const double* a0, const double* b0, const unsigned char* valid0, co
                                 long q = lin(xx, yy, zz, nx, ny);
                                 if (!valid[q]) continue;
                                 double ds = s[q] - s[i];
-                                double w = exp(-(ds * ds) / (h * h));
+                                double w = exp(-(ds * ds - d2min) / (h * h));
                                 sw += w;
                                 sa += w * A[q];
                                 sb += w * B[q];

@@ -108,8 +108,9 @@ void orc_gauss(const double* in, int nx, int ny, int nz, double sigma, double* o
  * [a_min, a_max]; masked voxels get a, b := 0 and are then filled, pass by
  * pass, with the Eq. 8-9 average over the voxels of the T region (inside
  * the volume) that are unmasked or were filled by an earlier pass, weights
- * exp(-(s_i - s_x)^2 / h^2) (Eq. 10). A voxel with no such neighbour (or a
- * zero weight sum) waits for the next pass. Passes stop when every voxel is
+ * exp(-(s_i - s_x)^2 / h^2) (Eq. 10), each divided by the largest of them
+ * (which leaves the Eq. 9 ratio unchanged and keeps it finite). A voxel with
+ * no such neighbour waits for the next pass. Passes stop when every voxel is
  * filled or after `passes`; a voxel still unfilled then keeps its Eq. 5-6
  * values. Writes A, B (N each), xi (N, may be NULL) and returns the number
  * of passes that filled at least one voxel. */

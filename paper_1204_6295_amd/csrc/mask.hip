@@ -33,12 +33,15 @@ constexpr int BX = 64;
 constexpr int BY = 4;
 constexpr float kLog2e = 1.44269504088896341f;
 
-// Eq. 10 weight exp(-dS^2 / h^2) = 2^(-dS^2 kw), kw = log2(e) / h^2, on the
-// hardware base-2 exponential (1 ulp; results below the smallest normal
-// float, |dS| > ~9.4 h, are 0). Shared by both fill kernels.
-__device__ inline float fill_weight(float ds, float kw)
+// Eq. 10 weight exp(-dS^2 / h^2) divided by the largest weight of the T
+// region, exp(-dmin^2 / h^2) with dmin the smallest |dS| over its valid
+// voxels: 2^(-kw (|dS| - dmin)(|dS| + dmin)), kw = log2(e) / h^2, on the
+// hardware base-2 exponential (1 ulp). The division leaves the Eq. 9 ratio
+// unchanged; the nearest intensity weighs exactly 1, so no weight sum
+// underflows and any voxel with a valid neighbour is filled.
+__device__ inline float fill_weight(float ad, float dmin, float kw)
 {
-    return __builtin_amdgcn_exp2f(-(ds * ds) * kw);
+    return __builtin_amdgcn_exp2f(-kw * ((ad - dmin) * (ad + dmin)));
 }
 
 inline dim3 grid_for(Dims d)
@@ -65,17 +68,24 @@ __global__ __launch_bounds__(BX* BY) void k_fill_pass(float2* __restrict__ ab, u
             const float h = consts[3];
             const float kw = kLog2e / (h * h);  // Eq. 10 weight as a power of 2
             const float sx = s[i];
-            double sw = 0.0, sa = 0.0, sb = 0.0;
             const int z0 = max(0, z - tz), z1 = min(nz - 1, z + tz);
             const int y0 = max(0, y - ty), y1 = min(ny - 1, y + ty);
             const int x0 = max(0, x - tx), x1 = min(nx - 1, x + tx);
+            float dmin = INFINITY;  // smallest |dS| over the valid voxels
+            for (int zz = z0; zz <= z1; ++zz)
+                for (int yy = y0; yy <= y1; ++yy) {
+                    const long row = ((long)zz * ny + yy) * nx;
+                    for (int xx = x0; xx <= x1; ++xx)
+                        if (stamp[row + xx] < pass) dmin = fminf(dmin, fabsf(s[row + xx] - sx));
+                }
+            double sw = 0.0, sa = 0.0, sb = 0.0;
             for (int zz = z0; zz <= z1; ++zz)
                 for (int yy = y0; yy <= y1; ++yy) {
                     const long row = ((long)zz * ny + yy) * nx;
                     for (int xx = x0; xx <= x1; ++xx) {
                         if (stamp[row + xx] >= pass) continue;
-                        const float ds = s[row + xx] - sx;
-                        const double w = (double)fill_weight(ds, kw);
+                        const float ad = fabsf(s[row + xx] - sx);
+                        const double w = (double)fill_weight(ad, dmin, kw);
                         const float2 v = ab[row + xx];
                         sw += w;
                         sa = fma(w, (double)v.x, sa);
@@ -185,6 +195,7 @@ __global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab,
     __shared__ int count;
     __shared__ int bb[4];
     __shared__ double3 part[FTX * FTY];  // partial sums of the row groups
+    __shared__ float dmins[FTX * FTY];   // smallest |dS| of the row groups
     if (stop && *stop) return;  // the level has met its stopping rule
     const int tx = CTX > 0 ? CTX : q.tx, ty = CTX > 0 ? CTY : q.ty, tz = CTX > 0 ? CTZ : q.tz, nz = q.nz;
     // region rows a wave loads per round trip: all of them for fixed T
@@ -281,24 +292,43 @@ __global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab,
         // sums in group order.
         const int RT = RD * (2 * ty + 1);  // region rows of one voxel
         const int S = min(3, (FTX * FTY) / n);
-        if ((int)threadIdx.x < n * S) {
-            const int v = (int)threadIdx.x % n, g = (int)threadIdx.x / n;
-            const int t = list[v];
-            const int vx = t % FTX, vy = t / FTX;
-            const float sx = s[((long)z * ny + (y0 + vy)) * nx + (x0 + vx)];
+        const bool item = (int)threadIdx.x < n * S;
+        const int v = item ? (int)threadIdx.x % n : 0, g = (int)threadIdx.x / n;
+        const int t = list[v];
+        const int vx = t % FTX, vy = t / FTX;
+        const float sx = item ? s[((long)z * ny + (y0 + vy)) * nx + (x0 + vx)] : 0.0f;
+        // 1: smallest |dS| over the valid voxels of this thread's rows, then
+        // over the voxel's groups (the reference of its Eq. 10 weights)
+        if (item) {
+            float dm = INFINITY;
+#pragma unroll 1
+            for (int r = g * RT / S; r < (g + 1) * RT / S; ++r) {
+                const int dz = r / (2 * ty + 1), dy = r - dz * (2 * ty + 1);
+                const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
+#pragma unroll
+                for (int dx = 0; dx <= 2 * tx; ++dx) {
+                    const float4 v4 = row[dx];
+                    const float ad = fabsf(v4.x - sx);
+                    dm = v4.w != 0.0f ? fminf(dm, ad) : dm;
+                }
+            }
+            dmins[threadIdx.x] = dm;
+        }
+        __syncthreads();
+        // 2: the weighted sums of the thread's rows in FP64
+        if (item) {
+            float dmin = dmins[v];
+            for (int k = 1; k < S; ++k) dmin = fminf(dmin, dmins[k * n + v]);
             double sw = 0.0, sa = 0.0, sb = 0.0;
 #pragma unroll 1
             for (int r = g * RT / S; r < (g + 1) * RT / S; ++r) {
                 const int dz = r / (2 * ty + 1), dy = r - dz * (2 * ty + 1);
                 const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
                 // branch-free: a voxel that is not valid adds an exact zero
-                // (its staged S, a, b are 0), so the sums equal those over
-                // the valid voxels alone
 #pragma unroll
                 for (int dx = 0; dx <= 2 * tx; ++dx) {
                     const float4 v4 = row[dx];
-                    const float ds = v4.x - sx;
-                    const float e = fill_weight(ds, kw);
+                    const float e = fill_weight(fabsf(v4.x - sx), dmin, kw);
                     const double w = (double)(v4.w != 0.0f ? e : 0.0f);
                     sw += w;
                     sa = fma(w, (double)v4.y, sa);

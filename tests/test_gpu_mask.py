@@ -71,6 +71,7 @@ def test_first_iteration_mask_and_fill(disc):
     ((20, 45, 70), (7, 7, 3), 10),
     ((20, 45, 70), (5, 9, 5), 4),
     ((12, 40, 36), (15, 15, 9), 3),  # T region too large for LDS: gathers from cache
+    ((48, 128, 128), (7, 7, 3), 10),  # 3072 fill tiles: each workgroup walks several queued tiles
 ])
 def test_fill_passes_and_regions(disc, shape, t, passes):
     """One iteration from r = 0 for several T regions and pass counts, on
@@ -81,9 +82,9 @@ def test_fill_passes_and_regions(disc, shape, t, passes):
     if shape == (48, 48, 48):
         ct, cb = _c1()
     else:
-        # pairs whose |m - S| and a stay at least 1e-4 (relative) from the
-        # thresholds, far beyond FP32 rounding
-        c = make_hn_pair(shape, pair={(20, 45, 70): 0, (12, 40, 36): 3}[shape])
+        # pairs whose |m - S| and a stay at least 4e-5 (relative) from the
+        # Eq. 7 thresholds, far beyond the FP32 rounding of |m - S| (3e-8)
+        c = make_hn_pair(shape, pair={(20, 45, 70): 0, (12, 40, 36): 3, (48, 128, 128): 5}[shape])
         ct, cb = c.ct, c.cbct
     kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(1,), mask_mode=1, fill_t=t, fill_passes=passes)
     reg = disc.Registration(**kw)

@@ -590,6 +590,27 @@ def test_fill_passes_jacobi_reach_and_leftover():
     assert used == n - 1 and np.all(A == 2.0)
 
 
+def test_fill_far_intensities_still_fill():
+    """Every Eq. 10 weight is positive, so a masked voxel with valid
+    neighbours is always filled, however far their intensities are: with
+    dS = 40 h and 41 h (exp(-1600) underflows in FP64) the fill is the Eq. 9
+    average whose weight ratio is exp(-(41^2 - 40^2)) = exp(-81); with a
+    single neighbour at dS = 50 h it is that neighbour's (a, b) exactly."""
+    h = 10.0
+    s = np.array([400.0, 0.0, -410.0]).reshape(1, 1, 3)
+    a0 = np.array([2.0, 0.0, 5.0]).reshape(s.shape)
+    b0 = np.array([-3.0, 0.0, 11.0]).reshape(s.shape)
+    valid = np.array([1, 0, 1], bool).reshape(s.shape)
+    A, B, used = oracle.fill(a0, b0, valid, s, h=h, t=(3, 1, 1), passes=1)
+    r = np.exp(-81.0)
+    assert used == 1
+    assert abs(A[0, 0, 1] - (2.0 + r * 5.0) / (1.0 + r)) < 1e-15
+    assert abs(B[0, 0, 1] - (-3.0 + r * 11.0) / (1.0 + r)) < 1e-14
+    s1 = np.array([500.0, 0.0]).reshape(1, 1, 2)
+    A, B, _ = oracle.fill(a0[..., :2], b0[..., :2], valid[..., :2], s1, h=h, t=(3, 1, 1), passes=1)
+    assert A[0, 0, 1] == 2.0 and B[0, 0, 1] == -3.0
+
+
 def test_fill_region_stays_inside_the_volume():
     """T counts only voxels inside the volume (no edge replication): with
     uniform s, x = 1 masked and radius 2 along x, the fill is the plain mean
