@@ -33,12 +33,12 @@ constexpr int BX = 64;
 constexpr int BY = 4;
 constexpr float kLog2e = 1.44269504088896341f;
 
-// Eq. 10 weight exp(-dS^2 / h^2) divided by the largest weight of the T
-// region, exp(-dmin^2 / h^2) with dmin the smallest |dS| over its valid
-// voxels: 2^(-kw (|dS| - dmin)(|dS| + dmin)), kw = log2(e) / h^2, on the
-// hardware base-2 exponential (1 ulp). The division leaves the Eq. 9 ratio
-// unchanged; the nearest intensity weighs exactly 1, so no weight sum
-// underflows and any voxel with a valid neighbour is filled.
+// Eq. 10 weight exp(-dS^2 / h^2) divided by exp(-dmin^2 / h^2):
+// 2^(-kw (|dS| - dmin)(|dS| + dmin)), kw = log2(e) / h^2, on the hardware
+// base-2 exponential (1 ulp). dmin = 0 gives the plain weight; dmin = the
+// smallest |dS| over the valid voxels of the T region makes the largest
+// weight exactly 1, so the sum cannot underflow. The Eq. 9 ratio is the same
+// for any dmin.
 __device__ inline float fill_weight(float ad, float dmin, float kw)
 {
     return __builtin_amdgcn_exp2f(-kw * ((ad - dmin) * (ad + dmin)));
@@ -297,65 +297,80 @@ __global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab,
         const int t = list[v];
         const int vx = t % FTX, vy = t / FTX;
         const float sx = item ? s[((long)z * ny + (y0 + vy)) * nx + (x0 + vx)] : 0.0f;
-        // 1: smallest |dS| over the valid voxels of this thread's rows, then
-        // over the voxel's groups (the reference of its Eq. 10 weights)
-        if (item) {
-            float dm = INFINITY;
+        // Weights relative to 2^0 first (the plain Eq. 10 weights); only if
+        // a listed voxel's weight sum comes out below 2^-60 (its nearest
+        // valid intensity is over ~6.5 h away, so weights may have
+        // underflowed) is the tile summed again relative to the largest
+        // weight of each voxel. Both give the Eq. 9 ratio.
+        double fw = 0.0, fa = 0.0, fb = 0.0;  // the own voxel's sums (thread < n)
+        for (int norm = 0; norm < 2; ++norm) {
+            if (norm) {
+                // smallest |dS| over the valid voxels of this thread's rows
+                if (item) {
+                    float dm = INFINITY;
 #pragma unroll 1
-            for (int r = g * RT / S; r < (g + 1) * RT / S; ++r) {
-                const int dz = r / (2 * ty + 1), dy = r - dz * (2 * ty + 1);
-                const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
+                    for (int r = g * RT / S; r < (g + 1) * RT / S; ++r) {
+                        const int dz = r / (2 * ty + 1), dy = r - dz * (2 * ty + 1);
+                        const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
 #pragma unroll
-                for (int dx = 0; dx <= 2 * tx; ++dx) {
-                    const float4 v4 = row[dx];
-                    const float ad = fabsf(v4.x - sx);
-                    dm = v4.w != 0.0f ? fminf(dm, ad) : dm;
+                        for (int dx = 0; dx <= 2 * tx; ++dx) {
+                            const float4 v4 = row[dx];
+                            const float ad = fabsf(v4.x - sx);
+                            dm = v4.w != 0.0f ? fminf(dm, ad) : dm;
+                        }
+                    }
+                    dmins[threadIdx.x] = dm;
                 }
+                __syncthreads();
             }
-            dmins[threadIdx.x] = dm;
-        }
-        __syncthreads();
-        // 2: the weighted sums of the thread's rows in FP64
-        if (item) {
-            float dmin = dmins[v];
-            for (int k = 1; k < S; ++k) dmin = fminf(dmin, dmins[k * n + v]);
-            double sw = 0.0, sa = 0.0, sb = 0.0;
+            // the weighted sums of the thread's rows in FP64
+            if (item) {
+                float dmin = 0.0f;
+                if (norm) {
+                    dmin = dmins[v];
+                    for (int k = 1; k < S; ++k) dmin = fminf(dmin, dmins[k * n + v]);
+                }
+                double sw = 0.0, sa = 0.0, sb = 0.0;
 #pragma unroll 1
-            for (int r = g * RT / S; r < (g + 1) * RT / S; ++r) {
-                const int dz = r / (2 * ty + 1), dy = r - dz * (2 * ty + 1);
-                const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
-                // branch-free: a voxel that is not valid adds an exact zero
+                for (int r = g * RT / S; r < (g + 1) * RT / S; ++r) {
+                    const int dz = r / (2 * ty + 1), dy = r - dz * (2 * ty + 1);
+                    const float4* row = reg + (dz * RH + vy + dy) * RW + vx;
+                    // branch-free: a voxel that is not valid adds an exact zero
 #pragma unroll
-                for (int dx = 0; dx <= 2 * tx; ++dx) {
-                    const float4 v4 = row[dx];
-                    const float e = fill_weight(fabsf(v4.x - sx), dmin, kw);
-                    const double w = (double)(v4.w != 0.0f ? e : 0.0f);
-                    sw += w;
-                    sa = fma(w, (double)v4.y, sa);
-                    sb = fma(w, (double)v4.z, sb);
+                    for (int dx = 0; dx <= 2 * tx; ++dx) {
+                        const float4 v4 = row[dx];
+                        const float e = fill_weight(fabsf(v4.x - sx), dmin, kw);
+                        const double w = (double)(v4.w != 0.0f ? e : 0.0f);
+                        sw += w;
+                        sa = fma(w, (double)v4.y, sa);
+                        sb = fma(w, (double)v4.z, sb);
+                    }
                 }
+                part[threadIdx.x] = make_double3(sw, sa, sb);
             }
-            part[threadIdx.x] = make_double3(sw, sa, sb);
+            __syncthreads();
+            bool redo = false;
+            if ((int)threadIdx.x < n) {
+                fw = fa = fb = 0.0;
+                for (int k = 0; k < S; ++k) {
+                    const double3 pg = part[k * n + threadIdx.x];
+                    fw += pg.x;
+                    fa += pg.y;
+                    fb += pg.z;
+                }
+                redo = fw < 0x1p-60;
+            }
+            if (norm || !__syncthreads_or(redo)) break;  // uniform
         }
-        __syncthreads();
         bool got = false;
         int gl = 0;  // tile-local index of the voxel this thread filled
-        if ((int)threadIdx.x < n) {
-            double sw = 0.0, sa = 0.0, sb = 0.0;
-            for (int g = 0; g < S; ++g) {
-                const double3 pg = part[g * n + threadIdx.x];
-                sw += pg.x;
-                sa += pg.y;
-                sb += pg.z;
-            }
-            if (sw > 0.0) {
-                const int t = list[threadIdx.x];
-                const long i = ((long)z * ny + (y0 + t / FTX)) * nx + (x0 + t % FTX);
-                ab[i] = make_float2((float)(sa / sw), (float)(sb / sw));
-                stamp[i] = (unsigned char)pass;
-                got = true;
-                gl = t;
-            }
+        if ((int)threadIdx.x < n && fw > 0.0) {
+            const int t = list[threadIdx.x];
+            const long i = ((long)z * ny + (y0 + t / FTX)) * nx + (x0 + t % FTX);
+            ab[i] = make_float2((float)(fa / fw), (float)(fb / fw));
+            stamp[i] = (unsigned char)pass;
+            got = true;
+            gl = t;
         }
         if (pass == passes || !__syncthreads_or(got)) continue;  // uniform
         // hand the filled voxels back to their own threads for the reach
