@@ -36,9 +36,9 @@ BYTES_PER_VOXEL = {
 ALGORITHMIC_MIN_BYTES = 32.0  # read CT, CBCT, r; write r (whole iteration)
 
 WORKLOADS = {
-    "hn256x256x96": dict(case="c2"),
-    "hn512x512x160": dict(case="c3"),
-    "ellipsoid48": dict(case="c1"),
+    "hn256x256x96": dict(case="hn256x256x96"),
+    "hn512x512x160": dict(case="hn512x512x160"),
+    "ellipsoid48": dict(case="ellipsoid48"),
 }
 
 
@@ -239,7 +239,7 @@ def main():
                     help="write the workload's CT and CBCT as raw float32 files (for the native driver) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs DISC on a single MI355X "
+        print("bench.py measures one GPU: DISC here runs on a single MI355X "
               "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("RANK", "0")) != 0:

@@ -52,7 +52,7 @@ typedef enum {
     DISC_ENOMEM = -2,   /* workspace smaller than disc_workspace_bytes() */
     DISC_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
     DISC_ESTATE = -4,   /* call out of order (e.g. iterate before set_volumes) */
-    DISC_ENOTSUP = -5   /* valid request outside what this build supports */
+    DISC_ENOTSUP = -5   /* valid request outside what the library supports */
 } disc_status;
 
 typedef struct {

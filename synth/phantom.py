@@ -31,13 +31,13 @@ SEED_BASE = 12046295
 # Workloads. shape is (nz, ny, nx); spacing is (dz, dy, dx) in mm.
 CONFIGS = {
     # 48^3 ellipsoid phantom, single resolution.
-    "c1": dict(cid=1, kind="ellipsoid", shape=(48, 48, 48), spacing=(1.0, 1.0, 1.0),
+    "ellipsoid48": dict(cid=1, kind="ellipsoid", shape=(48, 48, 48), spacing=(1.0, 1.0, 1.0),
                max_def_mm=3.0, patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,)),
     # head-and-neck-like 256 x 256 x 96, 1.95 x 1.95 x 2.5 mm.
-    "c2": dict(cid=2, kind="hn", shape=(96, 256, 256), spacing=(2.5, 1.953125, 1.953125),
+    "hn256x256x96": dict(cid=2, kind="hn", shape=(96, 256, 256), spacing=(2.5, 1.953125, 1.953125),
                max_def_mm=8.0, patch=(11, 11, 11), sigma=2.0, levels=3, iters=(100, 100, 100)),
     # clinical size 512 x 512 x 160, same field of view.
-    "c3": dict(cid=3, kind="hn", shape=(160, 512, 512), spacing=(1.5, 0.9765625, 0.9765625),
+    "hn512x512x160": dict(cid=3, kind="hn", shape=(160, 512, 512), spacing=(1.5, 0.9765625, 0.9765625),
                max_def_mm=12.0, patch=(15, 15, 15), sigma=2.0, levels=3, iters=(200, 200, 200)),
 }
 
@@ -300,7 +300,7 @@ def make_hn_pair(shape, pair=0, cid=2, max_def_mm=8.0, device="cpu", fov=HN_FOV)
 
 
 def make_case(name, pair=0, device="cpu"):
-    """Inputs of a named workload ('c1', 'c2', 'c3')."""
+    """Inputs of a named workload ('ellipsoid48', 'hn256x256x96', 'hn512x512x160')."""
     cfg = CONFIGS[name]
     if cfg["kind"] == "ellipsoid":
         case = make_ellipsoid_pair(cfg["shape"], pair=pair, cid=cfg["cid"], device=device,

@@ -51,7 +51,7 @@ def test_double_force_step(disc, shape, sigma):
 def test_double_force_registration(disc):
     from synth.phantom import make_case
 
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,), force_mode=1)
     reg = disc.Registration(**kw)
     reg.set_volumes(to_dev(c.ct), to_dev(c.cbct))
@@ -59,7 +59,7 @@ def test_double_force_registration(disc):
     r = to_np(reg.field())
     r_ref, f_ref = oracle.register(c.ct, c.cbct, oracle.make_params(**kw))
     emax, erms = field_err(r, r_ref)
-    print("double force c1: field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
+    print("double force 48^3: field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
     assert emax <= FIELD_MAX and erms <= FIELD_RMS
     assert rel_err(to_np(reg.corrected()), f_ref) <= 1e-3
     # the two forces give different fields
@@ -106,7 +106,7 @@ def _pick_eps(ct, cb, base, lag):
 def test_stopping_rule_matches_oracle(disc, levels, iters, shape):
     from synth.phantom import make_case, make_ellipsoid_pair
 
-    c = make_case("c1") if shape is None else make_ellipsoid_pair(shape, pair=3)
+    c = make_case("ellipsoid48") if shape is None else make_ellipsoid_pair(shape, pair=3)
     lag = 4
     base = dict(patch=(5, 5, 5), sigma=1.5, levels=levels, iters=iters)
     eps, ref = _pick_eps(c.ct, c.cbct, base, lag)
@@ -136,7 +136,7 @@ def test_stopping_rule_identical_images(disc):
     the field stays exactly zero."""
     from synth.phantom import make_case
 
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     reg = disc.Registration(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(30,), stop_eps=1e-4, stop_lag=6)
     reg.set_volumes(to_dev(c.ct), to_dev(c.ct))
     reg.run()

@@ -30,7 +30,7 @@ def scaled_err(gpu_pts, ref_pts, gpu_full):
     return float(np.abs(np.asarray(gpu_pts, np.float64) - ref_pts).max()) / (scale if scale > 0 else 1.0)
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
+@pytest.mark.parametrize("name", ["hn256x256x96", "hn512x512x160"])
 def test_steps_sampled_at_full_size(disc, name):
     from synth.phantom import CONFIGS, make_case
 
@@ -78,8 +78,8 @@ def test_full_schedule_c2_deterministic_and_sane(disc):
     Eq. 7-10 mask, both plain demons and DISC add spurious deformation."""
     from synth.phantom import CONFIGS, make_case
 
-    cfg = CONFIGS["c2"]
-    case = make_case("c2", device="cuda")
+    cfg = CONFIGS["hn256x256x96"]
+    case = make_case("hn256x256x96", device="cuda")
     ct, cb = to_dev(case.ct), to_dev(case.cbct)
     outs = []
     for _ in range(2):
@@ -100,7 +100,7 @@ def test_full_schedule_c2_deterministic_and_sane(disc):
     hist = lambda v: np.histogram(v[body], bins=bins)[0] / body.sum()  # noqa: E731
     h_raw = np.abs(hist(s_h) - hist(m_h)).sum()
     h_cor = np.abs(hist(f_h) - hist(m_h)).sum()
-    print("c2 mean |S - m| %.1f HU, mean |I's - m| %.1f HU; histogram L1 %.3f -> %.3f"
+    print("256x256x96 mean |S - m| %.1f HU, mean |I's - m| %.1f HU; histogram L1 %.3f -> %.3f"
           % (e_raw, e_cor, h_raw, h_cor))
     assert e_cor < 0.5 * e_raw
     assert h_cor < h_raw

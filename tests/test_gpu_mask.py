@@ -23,15 +23,15 @@ def disc():
     return d
 
 
-def _c1():
+def _ellipsoid48():
     from synth.phantom import make_case
 
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     return c.ct, c.cbct
 
 
 def test_mask_parameters_match_the_rules(disc):
-    ct, cb = _c1()
+    ct, cb = _ellipsoid48()
     reg = disc.Registration(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(1,), mask_mode=1)
     reg.set_volumes(to_dev(ct), to_dev(cb))
     mp = reg.mask_params()
@@ -47,7 +47,7 @@ def test_mask_parameters_match_the_rules(disc):
 def test_first_iteration_mask_and_fill(disc):
     """At r = 0 the deformed image is the CT itself, so the corrected image
     of the first iteration is Eq. 5-10 on known inputs: GPU vs oracle."""
-    ct, cb = _c1()
+    ct, cb = _ellipsoid48()
     reg = disc.Registration(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(1,), mask_mode=1)
     reg.set_volumes(to_dev(ct), to_dev(cb))
     reg.run()
@@ -80,7 +80,7 @@ def test_fill_passes_and_regions(disc, shape, t, passes):
     from synth.phantom import make_hn_pair
 
     if shape == (48, 48, 48):
-        ct, cb = _c1()
+        ct, cb = _ellipsoid48()
     else:
         # pairs whose |m - S| and a stay at least 4e-5 (relative) from the
         # Eq. 7 thresholds, far beyond the FP32 rounding of |m - S| (3e-8)
@@ -104,14 +104,14 @@ def test_fill_passes_and_regions(disc, shape, t, passes):
 
 
 def test_masked_registration_matches_oracle(disc):
-    ct, cb = _c1()
+    ct, cb = _ellipsoid48()
     kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,), mask_mode=1)
     reg = disc.Registration(**kw)
     reg.set_volumes(to_dev(ct), to_dev(cb))
     reg.run()
     r_ref, f_ref = oracle.register(ct, cb, oracle.make_params(**kw))
     emax, erms = field_err(to_np(reg.field()), r_ref)
-    print("masked c1: field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
+    print("masked 48^3: field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
     assert emax <= FIELD_MAX and erms <= FIELD_RMS
     assert rel_err(to_np(reg.corrected()), f_ref) <= 1e-3
 

@@ -32,12 +32,12 @@ def test_c1_matches_oracle(disc):
     """48^3 ellipsoid phantom, patch 5^3, sigma 1.5, one level, 20 iterations."""
     from synth.phantom import make_case
 
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(20,))
     reg, r, f = run_gpu(disc, c.ct, c.cbct, **kw)
     r_ref, f_ref = oracle.register(c.ct, c.cbct, oracle.make_params(**kw))
     emax, erms = field_err(r, r_ref)
-    print("c1 field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
+    print("48^3 field err max %.3g rms %.3g; |r| max %.3g" % (emax, erms, np.abs(r_ref).max()))
     assert emax <= FIELD_MAX and erms <= FIELD_RMS
     assert rel_err(f, f_ref) <= 1e-3
     assert np.abs(r_ref).max() > 0.5  # the registration actually moved
@@ -67,7 +67,7 @@ def test_identical_images_zero_update(disc):
     exactly zero through every level."""
     from synth.phantom import make_case
 
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     _, r, f = run_gpu(disc, c.ct, c.ct, patch=(5, 5, 5), sigma=1.5, levels=2, iters=(3, 3))
     assert np.all(r == 0.0)
     assert rel_err(f, c.ct) <= 1e-6
@@ -87,7 +87,7 @@ def test_affine_cbct_corrected_back(disc):
 def test_deterministic(disc):
     from synth.phantom import make_case
 
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     kw = dict(patch=(5, 5, 5), sigma=1.5, levels=2, iters=(5, 5))
     _, r1, f1 = run_gpu(disc, c.ct, c.cbct, **kw)
     _, r2, f2 = run_gpu(disc, c.ct, c.cbct, **kw)
@@ -99,7 +99,7 @@ def test_state_machine_and_errors(disc):
 
     from synth.phantom import make_case
 
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     reg = disc.Registration(patch=(5, 5, 5), sigma=1.5, levels=2, iters=(2, 3))
     with pytest.raises(disc.DiscError) as e:
         reg.iterate(1)

@@ -95,8 +95,8 @@ def test_sampled_grad_at_full_size(disc):
     state, from a realistic mid-registration field."""
     from synth.phantom import CONFIGS, make_case
 
-    cfg = CONFIGS["c2"]
-    case = make_case("c2", device="cuda")
+    cfg = CONFIGS["hn256x256x96"]
+    case = make_case("hn256x256x96", device="cuda")
     patch = cfg["patch"]
     ct, cb = to_dev(case.ct), to_dev(case.cbct)
     r = to_dev(0.6 * case.r_true)
@@ -106,7 +106,7 @@ def test_sampled_grad_at_full_size(disc):
     ref = oracle.ssd_grad_pts(to_np(ct), to_np(cb), to_np(r), patch, pts)
     scale = np.abs(grad).max()
     err = max(float(np.abs(grad[c].ravel()[pts].astype(np.float64) - ref[:, c]).max()) for c in range(3)) / scale
-    print("c2 sampled gradient rel error %.2g (scale %.3g)" % (err, scale))
+    print("256x256x96 sampled gradient rel error %.2g (scale %.3g)" % (err, scale))
     assert err <= GRAD_RTOL
 
 

@@ -272,7 +272,7 @@ def test_downsample_and_upsample():
 
 def test_identical_images_give_zero_update():
     """S = CT: Delta HU = 0, a = 1, b = 0, I'_s = CT, u = 0, r stays 0 exactly."""
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     ct = c.ct.astype(np.float64)
     p = oracle.make_params(patch=(5, 5, 5), sigma=1.5, levels=2, iters=(3, 3))
     r, f = oracle.register(ct, ct, p)
@@ -658,7 +658,7 @@ def test_mask_off_limits_and_identical_images():
     on (a = 1 everywhere, nothing masked)."""
     from synth.phantom import make_case
 
-    c = make_case("c1")
+    c = make_case("ellipsoid48")
     ct, cb = c.ct.astype(np.float64), c.cbct.astype(np.float64)
     base = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(4,))
     r0, f0 = oracle.register(ct, cb, oracle.make_params(**base))
