@@ -787,8 +787,8 @@ int disc_ssd_grad(const float* ct_dev, const float* ys_dev, const float* r_dev, 
     if (e == hipSuccess) e = disc::launch_ssd_moments(s.m, ys_dev, s.dres, s.a, s.partial, d, patch, st);
     if (e == hipSuccess) e = disc::launch_box_adjoint(s.a, s.b, d, 0, patch[0] / 2, st);
     if (e == hipSuccess) e = disc::launch_box_adjoint(s.b, s.a, d, 1, patch[1] / 2, st);
-    if (e == hipSuccess) e = disc::launch_box_adjoint(s.a, s.b, d, 2, patch[2] / 2, st);
-    if (e == hipSuccess) e = disc::launch_ssd_grad(ct_dev, r_dev, s.m, s.dres, s.b, scale_dev, grad_dev, d, st);
+    if (e == hipSuccess)
+        e = disc::launch_ssd_grad_z(ct_dev, r_dev, s.m, s.dres, s.a, scale_dev, grad_dev, d, patch[2] / 2, st);
     if (e == hipSuccess && loss_dev)
         e = disc::launch_ssd_finish(s.partial, disc::ssd_partial_count(d), loss_dev, st);
     return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "ssd gradient");

@@ -63,9 +63,11 @@ hipError_t launch_ssd_moments(const float* m, const float* ys, float* dres, doub
                               Dims d, const int patch[3], hipStream_t st);
 // Transpose of the clamped window sum of radius R along one axis (0 x, 1 y, 2 z).
 hipError_t launch_box_adjoint(const double2* in, double2* out, Dims d, int axis, int R, hipStream_t st);
-// grad = scale * (2 dres - 2 (m B(beta) + B(gamma))) * d trilinear / d position.
-hipError_t launch_ssd_grad(const float* ct, const float* r, const float* m, const float* dres,
-                           const double2* bg, const float* scale, float* grad, Dims d, hipStream_t st);
+// grad = scale * (2 dres - 2 (m B(beta) + B(gamma))) * d trilinear / d position,
+// with B = B_z B_y B_x: the z adjoint (radius R) of t = B_y B_x (beta, gamma)
+// is fused with the gradient.
+hipError_t launch_ssd_grad_z(const float* ct, const float* r, const float* m, const float* dres,
+                             const double2* t, const float* scale, float* grad, Dims d, int R, hipStream_t st);
 // loss = sum of n partial sums, fixed order.
 hipError_t launch_ssd_finish(const double* partial, int n, double* loss, hipStream_t st);
 

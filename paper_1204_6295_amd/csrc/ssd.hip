@@ -5,13 +5,16 @@
 // Backward data flow (patch moments are recomputed, never stored):
 //   warp                      m = CT(x + r)
 //   moments sweep (SSD mode)  D = m - I'_s, adjoint weights (beta, gamma)
-//   3 x box adjoint           B(beta), B(gamma): transpose of the clamped
-//                             patch sum, one axis per launch
-//   gradient                  dL/dm = 2 D - 2 (m B(beta) + B(gamma)), times
+//   2 x box adjoint           x, then y: transpose of the clamped patch sum,
+//                             one axis per launch
+//   z adjoint + gradient      B(beta), B(gamma) along each column, then
+//                             dL/dm = 2 D - 2 (m B(beta) + B(gamma)) times
 //                             the derivative of the trilinear interpolant
 // The adjoint sums stay in FP64: m B(beta) and B(gamma) cancel to the scale
 // of the patch deviation, which in near-flat patches is far below the
 // magnitude of either term.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace disc {
@@ -61,22 +64,15 @@ __global__ __launch_bounds__(BX* BY) void k_box_adjoint(const double2* __restric
     out[i] = make_double2(s1, s2);
 }
 
-// dL/dr = dL/dm * d m / d position, with dL/dm = 2 D - 2 (m B(beta) + B(gamma))
-// and the derivative of the trilinear interpolant of the warp (same floor
-// and clamp conventions: the cell is the one the warp samples).
-__global__ __launch_bounds__(BX* BY) void k_ssd_grad(const float* __restrict__ ct,
-                                                    const float* __restrict__ r,
-                                                    const float* __restrict__ m,
-                                                    const float* __restrict__ dres,
-                                                    const double2* __restrict__ bg,
-                                                    const float* __restrict__ scale,
-                                                    float* __restrict__ grad, int nx, int ny,
-                                                    int nz)
+// dL/dr at voxel (x, y, z) = dL/dm * d m / d position, with
+// dL/dm = 2 D - 2 (m B(beta) + B(gamma)) and the derivative of the trilinear
+// interpolant of the warp (same floor and clamp conventions: the cell is the
+// one the warp samples). b = (B(beta), B(gamma)) at the voxel.
+__device__ __forceinline__ void grad_at(const float* __restrict__ ct, const float* __restrict__ r,
+                                        const float* __restrict__ m, const float* __restrict__ dres,
+                                        const float* __restrict__ scale, float* __restrict__ grad, int x,
+                                        int y, int z, int nx, int ny, int nz, double2 b)
 {
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= nx || y >= ny) return;
     const long N = (long)nx * ny * nz;
     const long i = ((long)z * ny + y) * nx + x;
     const float rx = r[i], ry = r[N + i], rz = r[2 * N + i];
@@ -96,13 +92,65 @@ __global__ __launch_bounds__(BX* BY) void k_ssd_grad(const float* __restrict__ c
     const float gx = uz * (uy * (c001 - c000) + ty * (c011 - c010)) + tz * (uy * (c101 - c100) + ty * (c111 - c110));
     const float gy = uz * (ux * (c010 - c000) + tx * (c011 - c001)) + tz * (ux * (c110 - c100) + tx * (c111 - c101));
     const float gz = uy * (ux * (c100 - c000) + tx * (c101 - c001)) + ty * (ux * (c110 - c010) + tx * (c111 - c011));
-    const double2 b = bg[i];
     const double G = 2.0 * ((double)dres[i] - fma((double)m[i], b.x, b.y));
     const double s = scale ? (double)scale[0] : 1.0;
     const double sg = s * G;
     grad[i] = (float)(sg * (double)gx);
     grad[N + i] = (float)(sg * (double)gy);
     grad[2 * N + i] = (float)(sg * (double)gz);
+}
+
+// The z adjoint fused with the gradient: a thread walks its column through
+// a chunk of zchunk planes, keeping the in-range z window sum of the x-y
+// adjoint t (see k_box_adjoint) as a running sum; the end planes take the
+// clamp's folded offsets by a direct sum. The gradient then follows at each
+// voxel without B(beta), B(gamma) going through memory.
+__global__ __launch_bounds__(BX* BY) void k_ssd_grad_z(const float* __restrict__ ct,
+                                                      const float* __restrict__ r,
+                                                      const float* __restrict__ m,
+                                                      const float* __restrict__ dres,
+                                                      const double2* __restrict__ t,
+                                                      const float* __restrict__ scale,
+                                                      float* __restrict__ grad, int nx, int ny,
+                                                      int nz, int R, int zchunk)
+{
+    const int x = blockIdx.x * BX + threadIdx.x;
+    const int y = blockIdx.y * BY + threadIdx.y;
+    const int za = blockIdx.z * zchunk, zb = min(nz, za + zchunk);
+    if (x >= nx || y >= ny) return;
+    const long plane = (long)nx * ny;
+    const double2* col = t + (long)y * nx + x;
+    double s1 = 0.0, s2 = 0.0;
+    for (int zz = max(0, za - R); zz <= min(nz - 1, za + R); ++zz) {
+        const double2 v = col[zz * plane];
+        s1 += v.x;
+        s2 += v.y;
+    }
+    for (int z = za; z < zb; ++z) {
+        if (z > za) {
+            if (z + R <= nz - 1) {
+                const double2 v = col[(z + R) * plane];
+                s1 += v.x;
+                s2 += v.y;
+            }
+            if (z - 1 - R >= 0) {
+                const double2 v = col[(z - 1 - R) * plane];
+                s1 -= v.x;
+                s2 -= v.y;
+            }
+        }
+        double2 b = make_double2(s1, s2);
+        if (z == 0 || z == nz - 1) {
+            b = make_double2(0.0, 0.0);
+            for (int zz = max(0, z - R); zz <= min(nz - 1, z + R); ++zz) {
+                const int c = nz == 1 ? 2 * R + 1 : (z == 0 ? R - zz + 1 : R - (nz - 1 - zz) + 1);
+                const double2 v = col[zz * plane];
+                b.x = fma((double)c, v.x, b.x);
+                b.y = fma((double)c, v.y, b.y);
+            }
+        }
+        grad_at(ct, r, m, dres, scale, grad, x, y, z, nx, ny, nz, b);
+    }
 }
 
 // Loss = sum of the per-workgroup partial sums, in a fixed order.
@@ -136,11 +184,15 @@ hipError_t launch_box_adjoint(const double2* in, double2* out, Dims d, int axis,
     return hipGetLastError();
 }
 
-hipError_t launch_ssd_grad(const float* ct, const float* r, const float* m, const float* dres,
-                           const double2* bg, const float* scale, float* grad, Dims d, hipStream_t st)
+hipError_t launch_ssd_grad_z(const float* ct, const float* r, const float* m, const float* dres,
+                             const double2* t, const float* scale, float* grad, Dims d, int R, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ssd_grad, grid_for(d), dim3(BX, BY), 0, st, ct, r, m, dres, bg, scale, grad,
-                       d.nx, d.ny, d.nz);
+    // about 8 planes per chunk: enough workgroups, short window warm-ups
+    const int chunks = std::max(1, (d.nz + 7) / 8);
+    const int zchunk = (d.nz + chunks - 1) / chunks;
+    const dim3 g((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + zchunk - 1) / zchunk);
+    hipLaunchKernelGGL(k_ssd_grad_z, g, dim3(BX, BY), 0, st, ct, r, m, dres, t, scale, grad, d.nx, d.ny, d.nz,
+                       R, zchunk);
     return hipGetLastError();
 }
 
