@@ -566,10 +566,11 @@ hipError_t launch_plane(const PlaneArgs& a, int R, hipStream_t st)
     return hipGetLastError();
 }
 
-// z chunks: about `target` workgroups in the launch (measured best at 8192
-// for the 256x256x96 registration: the fused warp's gathers want many waves
-// in flight); re-read halo planes come from cache.
-ZArgs z_args(const float* q, float* out, Dims d, const GaussTaps& t, int target = 8192)
+// z chunks: about `target` workgroups in the launch (measured best at 4096
+// for the 256x256x96 registration: 6-plane chunks re-read 2R halo planes
+// per 6 outputs, and still leave enough waves in flight for the fused
+// warp's gathers); re-read halo planes come from cache.
+ZArgs z_args(const float* q, float* out, Dims d, const GaussTaps& t, int target = 4096)
 {
     ZArgs a;
     a.q = q;
