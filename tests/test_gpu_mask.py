@@ -70,6 +70,8 @@ def test_first_iteration_mask_and_fill(disc):
     ((48, 48, 48), (7, 7, 3), 1),
     ((20, 45, 70), (7, 7, 3), 10),
     ((20, 45, 70), (5, 9, 5), 4),
+    ((20, 45, 70), (1, 1, 1), 2),  # T is the voxel itself: nothing can be filled
+    ((20, 45, 70), (13, 13, 3), 3),  # generic work-list kernel, reach of one tile in x
     ((12, 40, 36), (15, 15, 9), 3),  # T region too large for LDS: gathers from cache
     ((48, 128, 128), (7, 7, 3), 10),  # 3072 fill tiles: each workgroup walks several queued tiles
 ])
@@ -100,6 +102,8 @@ def test_fill_passes_and_regions(disc, shape, t, passes):
     print("%s T %s passes %d: masked %.3f, used %d, rel %.3g" % (shape, t, passes, xi.mean(), used,
                                                                  rel_err(f, f_ref)))
     assert xi.any() and (~xi).any()
+    if t == (1, 1, 1):
+        assert used == 0
     assert rel_err(f, f_ref) <= 1e-4
 
 
