@@ -442,14 +442,15 @@ MAX_BATCH = 16
 
 class Batch:
     """Independent CT/CBCT pairs of uneven sizes advanced together (one
-    resolution level): four batched launches per iteration, optionally
-    replayed from a captured HIP graph."""
+    resolution level): three batched launches per iteration (the CT is
+    warped once after set-up, then by each iteration's z pass), optionally
+    replayed from a captured HIP graph. force_mode 1 takes both Eq. 1 terms."""
 
     def __init__(self, shapes, patch=(11, 11, 11), sigma=2.0, iters=100, global_shift=True,
-                 var_floor=1e-2, diff_floor=1e-3):
+                 var_floor=1e-2, diff_floor=1e-3, force_mode=0):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.params = make_params(patch=patch, sigma=sigma, levels=1, iters=(iters,), global_shift=global_shift,
-                                  var_floor=var_floor, diff_floor=diff_floor)
+                                  var_floor=var_floor, diff_floor=diff_floor, force_mode=force_mode)
         n = len(self.shapes)
         dims = (ctypes.c_int * (3 * n))(*[d for (nz, ny, nx) in self.shapes for d in (nx, ny, nz)])
         h = _V()

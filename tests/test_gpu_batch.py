@@ -79,6 +79,28 @@ def test_batch_pair_matches_oracle(disc, pairs):
     assert emax <= FIELD_MAX and erms <= FIELD_RMS
 
 
+def test_double_force_batch_and_new_volumes(disc, pairs):
+    """Both Eq. 1 terms in a batch equal the single-volume path; new volumes
+    on the same batch restart from a fresh warp: identical images then keep
+    the field exactly zero."""
+    cts = [to_dev(p[0]) for p in pairs]
+    cbs = [to_dev(p[1]) for p in pairs]
+    b = disc.Batch(SHAPES, patch=PATCH, sigma=SIGMA, iters=ITERS, force_mode=1)
+    b.set_volumes(cts, cbs)
+    b.run(use_graph=True)
+    for v in range(len(SHAPES)):
+        reg = disc.Registration(patch=PATCH, sigma=SIGMA, levels=1, iters=(ITERS,), force_mode=1)
+        reg.set_volumes(cts[v], cbs[v])
+        reg.run()
+        emax, erms = field_err(to_np(b.field(v)), to_np(reg.field()))
+        print("double force pair %d: field max %.2g rms %.2g" % (v, emax, erms))
+        assert emax <= FIELD_MAX and erms <= FIELD_RMS
+    b.set_volumes(cts, cts)
+    b.run(use_graph=True)
+    for v in range(len(SHAPES)):
+        assert float(b.field(v).abs().max()) == 0.0
+
+
 def test_graph_replay_equals_eager(disc, pairs):
     cts = [to_dev(p[0]) for p in pairs]
     cbs = [to_dev(p[1]) for p in pairs]
