@@ -553,8 +553,9 @@ hipError_t launch_fill_pass(float2* ab, unsigned char* stamp, const float* s, co
 {
     size_t lds;
     if (fill_lists_fit(t, &lds)) {
-        // a grid of at most a few workgroups per CU walks the queued tiles
-        const unsigned grid = (unsigned)std::min(fill_tiles(d), 2048);
+        // up to 8192 workgroups walk the queued tiles: about one tile each at
+        // 256x256x96, so the hardware dispatcher balances uneven tiles
+        const unsigned grid = (unsigned)std::min(fill_tiles(d), 8192);
         if (t[0] == 7 && t[1] == 7 && t[2] == 3)  // the 7 x 7 x 3 region of Sec. 2.3
             hipLaunchKernelGGL((k_fill_list<3, 3, 1>), dim3(grid), dim3(FTX * FTY), lds, st, ab, stamp, s, consts,
                                make_q(fl, d, t), pass, passes, d.nx, d.ny, stop);

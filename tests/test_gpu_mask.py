@@ -73,7 +73,8 @@ def test_first_iteration_mask_and_fill(disc):
     ((20, 45, 70), (1, 1, 1), 2),  # T is the voxel itself: nothing can be filled
     ((20, 45, 70), (13, 13, 3), 3),  # generic work-list kernel, reach of one tile in x
     ((12, 40, 36), (15, 15, 9), 3),  # T region too large for LDS: gathers from cache
-    ((48, 128, 128), (7, 7, 3), 10),  # 3072 fill tiles: each workgroup walks several queued tiles
+    ((48, 128, 128), (7, 7, 3), 10),  # 3072 fill tiles
+    ((40, 256, 256), (7, 7, 3), 10),  # 10240 fill tiles, more than the workgroups of a pass
 ])
 def test_fill_passes_and_regions(disc, shape, t, passes):
     """One iteration from r = 0 for several T regions and pass counts, on
@@ -86,7 +87,8 @@ def test_fill_passes_and_regions(disc, shape, t, passes):
     else:
         # pairs whose |m - S| and a stay at least 4e-5 (relative) from the
         # Eq. 7 thresholds, far beyond the FP32 rounding of |m - S| (3e-8)
-        c = make_hn_pair(shape, pair={(20, 45, 70): 0, (12, 40, 36): 3, (48, 128, 128): 5}[shape])
+        c = make_hn_pair(shape, pair={(20, 45, 70): 0, (12, 40, 36): 3, (48, 128, 128): 5,
+                                       (40, 256, 256): 3}[shape])
         ct, cb = c.ct, c.cbct
     kw = dict(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(1,), mask_mode=1, fill_t=t, fill_passes=passes)
     reg = disc.Registration(**kw)
