@@ -287,11 +287,11 @@ __global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab,
         }
         __syncthreads();
         // Each listed voxel's T region is split into S groups of region rows
-        // (S <= 3, as many as the workgroup has threads for); a thread sums
+        // (S <= 7, as many as the workgroup has threads for); a thread sums
         // one group in FP64, and the voxel's own thread adds the S partial
         // sums in group order.
         const int RT = RD * (2 * ty + 1);  // region rows of one voxel
-        const int S = min(3, (FTX * FTY) / n);
+        const int S = min(7, (FTX * FTY) / n);
         const bool item = (int)threadIdx.x < n * S;
         const int v = item ? (int)threadIdx.x % n : 0, g = (int)threadIdx.x / n;
         const int t = list[v];
