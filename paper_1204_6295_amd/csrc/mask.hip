@@ -196,6 +196,7 @@ __global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab,
     __shared__ int bb[4];
     __shared__ double3 part[FTX * FTY];  // partial sums of the row groups
     __shared__ float dmins[FTX * FTY];   // smallest |dS| of the row groups
+    __shared__ unsigned char zxa[(FTY + 2 * 7) * FTX];  // the x-window OR of zany (ty <= 7)
     if (stop && *stop) return;  // the level has met its stopping rule
     const int tx = CTX > 0 ? CTX : q.tx, ty = CTX > 0 ? CTY : q.ty, tz = CTX > 0 ? CTZ : q.tz, nz = q.nz;
     // region rows a wave loads per round trip: all of them for fixed T
@@ -245,15 +246,20 @@ __global__ __launch_bounds__(FTX* FTY) void k_fill_list(float2* __restrict__ ab,
             zany[k] = o;
         }
         __syncthreads();
+        // then along x over the window, for the tile's columns (ty < 8)
+        for (int k = threadIdx.x; k < RH * FTX; k += FTX * FTY) {
+            const int yy = k / FTX, xx = k - yy * FTX;
+            const unsigned char* row = zany + yy * RW + xx;
+            unsigned char o = 0;
+            for (int dx = 0; dx <= 2 * tx; ++dx) o |= row[dx];
+            zxa[k] = o;
+        }
+        __syncthreads();
         const bool inside = x0 + lx < nx && y0 + ly < ny;
         const bool mine = inside && rst[(tz * RH + ly + ty) * RW + lx + tx] == 255;
         bool need = false;
-        if (mine) {
-            for (int dy = 0; dy <= 2 * ty && !need; ++dy) {
-                const unsigned char* row = zany + (ly + dy) * RW + lx;
-                for (int dx = 0; dx <= 2 * tx; ++dx) need |= row[dx] != 0;
-            }
-        }
+        if (mine)
+            for (int dy = 0; dy <= 2 * ty; ++dy) need |= zxa[(ly + dy) * FTX + lx] != 0;
         const unsigned long long nb = __ballot(need);
         int base = 0;
         if (lane == 0 && nb) base = atomicAdd(&count, (int)__popcll(nb));
