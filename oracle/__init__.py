@@ -124,6 +124,8 @@ def lib():
         _U8 = ctypes.POINTER(ctypes.c_ubyte)
         L.orc_fill.restype = ctypes.c_int
         L.orc_fill.argtypes = [_D, _D, _U8, _D, _I, _I, _I, ctypes.c_double, _IP, _I, _D, _D]
+        L.orc_fill_ex.restype = ctypes.c_int
+        L.orc_fill_ex.argtypes = [_D, _D, _U8, _D, _I, _I, _I, ctypes.c_double, _IP, _I, _D, _D, _U8]
         L.orc_mask_fill.restype = ctypes.c_int
         L.orc_mask_fill.argtypes = [_D, _D, _D, _D, _D, _D, _I, _I, _I, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, _IP, _I, _D, _D, _U8]
@@ -403,6 +405,25 @@ def fill(a0, b0, valid0, s, h, t=(7, 7, 3), passes=10):
     used = lib().orc_fill(pa, pb, v.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), ps, nx, ny, nz, float(h), tt,
                           int(passes), A.ctypes.data_as(_D), B.ctypes.data_as(_D))
     return A, B, used
+
+
+def fill_ex(a0, b0, valid0, s, h, t=(7, 7, 3), passes=10):
+    """orc_fill with the pass that filled each voxel: returns (A, B, passes
+    used, pass_of) with pass_of 0 = valid from the start, p = filled by pass
+    p (1-based), 255 = never filled."""
+    a0, pa = _d(a0)
+    b0, pb = _d(b0)
+    s, ps = _d(s)
+    v = np.ascontiguousarray(valid0, dtype=np.uint8)
+    nx, ny, nz = _dims(s)
+    A = np.empty_like(s)
+    B = np.empty_like(s)
+    pass_of = np.empty(s.shape, dtype=np.uint8)
+    tt = (ctypes.c_int * 3)(*[int(x) for x in t])
+    _U8 = ctypes.POINTER(ctypes.c_ubyte)
+    used = lib().orc_fill_ex(pa, pb, v.ctypes.data_as(_U8), ps, nx, ny, nz, float(h), tt, int(passes),
+                             A.ctypes.data_as(_D), B.ctypes.data_as(_D), pass_of.ctypes.data_as(_U8))
+    return A, B, used, pass_of
 
 
 def mask_fill(m, s, patch, tau, hu0, a_min, a_max, h, t=(7, 7, 3), passes=10):

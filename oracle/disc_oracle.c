@@ -307,6 +307,13 @@ void orc_force_double(const double* m, const double* f, int nx, int ny, int nz,
 int orc_fill(const double* a0, const double* b0, const unsigned char* valid0, const double* s,
              int nx, int ny, int nz, double h, const int t[3], int passes, double* A, double* B)
 {
+    return orc_fill_ex(a0, b0, valid0, s, nx, ny, nz, h, t, passes, A, B, NULL);
+}
+
+int orc_fill_ex(const double* a0, const double* b0, const unsigned char* valid0, const double* s,
+                int nx, int ny, int nz, double h, const int t[3], int passes, double* A, double* B,
+                unsigned char* pass_of)
+{
     long n = (long)nx * ny * nz;
     int tx = t[0] / 2, ty = t[1] / 2, tz = t[2] / 2;
     unsigned char* valid = (unsigned char*)malloc(n);
@@ -318,6 +325,7 @@ int orc_fill(const double* a0, const double* b0, const unsigned char* valid0, co
         /* Eq. 7 paragraph: masked voxels start from a = b = 0 */
         A[i] = valid[i] ? a0[i] : 0.0;
         B[i] = valid[i] ? b0[i] : 0.0;
+        if (pass_of) pass_of[i] = valid[i] ? 0 : 255;
     }
     int used = 0;
     for (int pass = 0; pass < passes; ++pass) {
@@ -367,6 +375,7 @@ int orc_fill(const double* a0, const double* b0, const unsigned char* valid0, co
                         nA[i] = sa / sw;
                         nB[i] = sb / sw;
                         nvalid[i] = 1;
+                        if (pass_of) pass_of[i] = (unsigned char)(pass + 1);
                         filled += 1;
                     }
                 }

@@ -19,8 +19,8 @@
  * Parity status: every function here is pinned by the CPU test-suite
  * (library routines, closed forms, invariants, brute force, and central
  * finite differences for the SSD gradient, closed forms of the double
- * force and of the stopping rule). The Eq. 7-10 mask/fill is not part of
- * this oracle.
+ * force and of the stopping rule, a hand-worked Eq. 8-10 average and the
+ * pass-by-pass reach of the Eq. 7-10 fill).
  */
 #ifndef DISC_ORACLE_H
 #define DISC_ORACLE_H
@@ -123,6 +123,13 @@ int orc_mask_fill(const double* m, const double* s, const double* mu_m, const do
  * valid0[x] (1 = unmasked): same passes and leftover rule as above. */
 int orc_fill(const double* a0, const double* b0, const unsigned char* valid0, const double* s,
              int nx, int ny, int nz, double h, const int t[3], int passes, double* A, double* B);
+
+/* orc_fill that also records, per voxel, the pass that filled it: 0 for a
+ * voxel valid from the start, p (1-based) for one filled by pass p, 255 for
+ * one never filled (pass_of may be NULL). */
+int orc_fill_ex(const double* a0, const double* b0, const unsigned char* valid0, const double* s,
+                int nx, int ny, int nz, double h, const int t[3], int passes, double* A, double* B,
+                unsigned char* pass_of);
 
 /* a_m of Sec. 2.3: the median of a = STD(M)/STD(S) (Eq. 5) over the voxels
  * where neither patch is flat (var > tau: a flat CT patch gives a = 0, which

@@ -336,6 +336,39 @@ def test_known_translation():
     assert np.linalg.norm(med(rd) - t) < 0.25 * np.linalg.norm(t)
 
 
+def _box_moments(v, patch):
+    """Patch mean and population variance over the clamped patch (scipy)."""
+    size = (patch[2], patch[1], patch[0])
+    mu = ndi.uniform_filter(v, size=size, mode="nearest")
+    return mu, ndi.uniform_filter(v * v, size=size, mode="nearest") - mu * mu
+
+
+def _literal_iteration(ct, s, mu_s, var_s, r, patch, sigma, tau=1e-2, eps=1e-3):
+    """One DISC iteration (Algorithm A1 steps 1, 3-6) composed from library
+    routines: map_coordinates warp, uniform_filter moments, Eq. 5-6,
+    clipped central differences for Eq. 1, gaussian_filter. Returns (r, m, f)."""
+    shape = ct.shape
+    R = int(np.ceil(3 * sigma))
+    z, y, x = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    m = ndi.map_coordinates(ct, np.stack([z + r[2], y + r[1], x + r[0]]), order=1, mode="nearest")
+    mu_m, var_m = _box_moments(m, patch)
+    a = np.where(var_s > tau, np.sqrt(np.maximum(var_m, 0) / np.where(var_s > tau, var_s, 1.0)), 1.0)
+    f = a * s + (mu_m - a * mu_s)
+    grads = []
+    for ax in (2, 1, 0):
+        n = shape[ax]
+        up = np.take(f, np.clip(np.arange(n) + 1, 0, n - 1), axis=ax)
+        dn = np.take(f, np.clip(np.arange(n) - 1, 0, n - 1), axis=ax)
+        grads.append((up - dn) / 2)
+    d = m - f
+    den = grads[0] ** 2 + grads[1] ** 2 + grads[2] ** 2 + d * d
+    ok = (den > 0) & (np.abs(d) >= eps)
+    u = np.stack([np.where(ok, d * gq / np.where(den > 0, den, 1), 0.0) for gq in grads])
+    rt = r - u
+    r = np.stack([ndi.gaussian_filter(rt[c], sigma, mode="nearest", radius=R) for c in range(3)])
+    return r, m, f
+
+
 def test_literal_iteration_matches_oracle():
     """An independent composition of library routines (map_coordinates,
     uniform_filter, clipped central differences, gaussian_filter) equals
@@ -344,38 +377,64 @@ def test_literal_iteration_matches_oracle():
     shape = (12, 12, 12)
     ct = g.normal(size=shape) * 300
     s = 0.9 * ndi.shift(ct, (0.3, -0.6, 0.8), order=1, mode="nearest") + 40 + g.normal(size=shape) * 10
-    patch, sigma, tau, eps = (3, 5, 3), 1.5, 1e-2, 1e-3
-    size = (patch[2], patch[1], patch[0])
-    R = int(np.ceil(3 * sigma))
-
-    def box(v):
-        mu = ndi.uniform_filter(v, size=size, mode="nearest")
-        return mu, ndi.uniform_filter(v * v, size=size, mode="nearest") - mu * mu
-
-    mu_s, var_s = box(s)
+    patch, sigma = (3, 5, 3), 1.5
+    mu_s, var_s = _box_moments(s, patch)
     r = np.zeros((3,) + shape)
-    z, y, x = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
     for _ in range(3):
-        m = ndi.map_coordinates(ct, np.stack([z + r[2], y + r[1], x + r[0]]), order=1, mode="nearest")
-        mu_m, var_m = box(m)
-        a = np.where(var_s > tau, np.sqrt(np.maximum(var_m, 0) / var_s), 1.0)
-        f = a * s + (mu_m - a * mu_s)
-        grads = []
-        for ax in (2, 1, 0):
-            n = shape[ax]
-            up = np.take(f, np.clip(np.arange(n) + 1, 0, n - 1), axis=ax)
-            dn = np.take(f, np.clip(np.arange(n) - 1, 0, n - 1), axis=ax)
-            grads.append((up - dn) / 2)
-        d = m - f
-        den = grads[0] ** 2 + grads[1] ** 2 + grads[2] ** 2 + d * d
-        ok = (den > 0) & (np.abs(d) >= eps)
-        u = np.stack([np.where(ok, d * gq / np.where(den > 0, den, 1), 0.0) for gq in grads])
-        rt = r - u
-        r = np.stack([ndi.gaussian_filter(rt[c], sigma, mode="nearest", radius=R) for c in range(3)])
+        r, m, f = _literal_iteration(ct, s, mu_s, var_s, r, patch, sigma)
     ro, mo, fo, _ = oracle.iterate(ct, s, np.zeros((3,) + shape), oracle.make_params(patch=patch, sigma=sigma), n=3)
     np.testing.assert_allclose(mo, m, atol=1e-9)
     np.testing.assert_allclose(fo, f, atol=1e-8)
     np.testing.assert_allclose(ro, r, atol=1e-9)
+
+
+def _block_mean2(v):
+    """2x2x2 block mean with the last plane repeated on odd extents (numpy)."""
+    pad = np.pad(v, [(0, n % 2) for n in v.shape], mode="edge")
+    nz, ny, nx = pad.shape
+    return pad.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(1, 3, 5))
+
+
+def _upsample2(rc, fine):
+    """r_fine = 2 trilinear(r_coarse, (x + 1/2)/2 - 1/2), edge replicated (scipy)."""
+    z, y, x = np.meshgrid(*[(np.arange(n) + 0.5) / 2 - 0.5 for n in fine], indexing="ij")
+    return np.stack([2 * ndi.map_coordinates(rc[c], np.stack([z, y, x]), order=1, mode="nearest")
+                     for c in range(3)])
+
+
+@pytest.mark.parametrize("shape,levels,iters,shift", [
+    ((10, 13, 16), 3, (3, 2, 2), True),
+    ((9, 12, 11), 2, (4, 3), False),
+])
+def test_level_schedule_matches_composition(shape, levels, iters, shift):
+    """The whole Algorithm A1 schedule (Sec. 2.3): global shift, block-mean
+    pyramid, r = 0 at the coarsest level, the per-level iteration with the
+    static moments of that level, and the x2 trilinear up-sampling of the
+    field at every level switch -- composed independently from numpy/scipy
+    on odd and even dims -- equals orc_register. A dropped up-sampling, a
+    field restarted at zero, a missing factor 2 or a level run with the
+    wrong static image each changes the final field."""
+    g = rng(40)
+    ct = ndi.gaussian_filter(g.normal(size=shape), 1.0) * 900 + 50
+    s0 = 0.8 * ndi.shift(ct, (0.4, -0.7, 0.5), order=1, mode="nearest") - 130 + g.normal(size=shape) * 15
+    patch, sigma = (3, 3, 3), 1.0
+    s = s0 + (ct.mean() - s0.mean()) if shift else s0.copy()
+    cts, ss = [ct], [s]
+    for _ in range(levels - 1):
+        cts.insert(0, _block_mean2(cts[0]))
+        ss.insert(0, _block_mean2(ss[0]))
+    r = np.zeros((3,) + cts[0].shape)
+    for lv in range(levels):
+        if lv > 0:
+            r = _upsample2(r, cts[lv].shape)
+        mu_s, var_s = _box_moments(ss[lv], patch)
+        for _ in range(iters[lv]):
+            r, m, f = _literal_iteration(cts[lv], ss[lv], mu_s, var_s, r, patch, sigma)
+    p = oracle.make_params(patch=patch, sigma=sigma, levels=levels, iters=iters, global_shift=shift)
+    ro, fo = oracle.register(ct, s0, p)
+    assert np.abs(r).max() > 0.05  # the schedule moved the field
+    np.testing.assert_allclose(ro, r, atol=1e-9)
+    np.testing.assert_allclose(fo, f, atol=1e-8 * np.abs(f).max())
 
 
 def test_point_evaluators_agree_with_whole_volume():
@@ -588,6 +647,11 @@ def test_fill_passes_jacobi_reach_and_leftover():
     assert np.array_equal(A[0, 0, 4:], a0[0, 0, 4:]) and np.array_equal(B[0, 0, 4:], b0[0, 0, 4:])
     A, _, used = oracle.fill(a0, b0, valid, s, h=50.0, t=(3, 1, 1), passes=20)
     assert used == n - 1 and np.all(A == 2.0)
+    # the pass that filled each voxel: x = p in pass p, 255 past the last pass
+    A2, B2, used2, pass_of = oracle.fill_ex(a0, b0, valid, s, h=50.0, t=(3, 1, 1), passes=3)
+    assert used2 == 3 and np.array_equal(pass_of[0, 0], [0, 1, 2, 3, 255, 255, 255, 255])
+    ref_a, ref_b, _ = oracle.fill(a0, b0, valid, s, h=50.0, t=(3, 1, 1), passes=3)
+    assert np.array_equal(A2, ref_a) and np.array_equal(B2, ref_b)
 
 
 def test_fill_far_intensities_still_fill():
