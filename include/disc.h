@@ -156,6 +156,14 @@ int disc_get_stats(disc_ctx* c, int level, int* iters_done, double* l_hist, int 
  * Synchronises `stream`. */
 int disc_get_mask_params(disc_ctx* c, float out[5], void* stream);
 
+/* Mask mode: the Eq. 7 mask and the Eq. 8-10 fill of the most recent
+ * iteration at the current level, one byte per voxel ([nz][ny][nx]) to
+ * out_dev: 0 = not masked (Eq. 5-6 a, b), p in 1..fill_passes = masked and
+ * filled by fill pass p, 255 = masked and never filled (keeps its Eq. 5-6
+ * a, b). DISC_ENOTSUP when mask_mode is 0; DISC_ESTATE before the first
+ * iteration of the current level. */
+int disc_get_mask(disc_ctx* c, unsigned char* out_dev, void* stream);
+
 /* ---- single steps, running the same kernels as disc_iterate ------------ */
 /* All buffers are caller-owned device memory of the stated sizes; inputs
  * and outputs must not overlap. N = nx * ny * nz. */
@@ -184,10 +192,13 @@ int disc_step_correct(const float* m_dev, const float* ys_dev, int nx, int ny, i
  * zero where |m - f| < diff_floor (central differences, clamped), then
  * r_out = G_sigma * rt per component. q is 3N floats of scratch (the
  * xy-filtered field); rt (may be NULL) receives r - u. m, f: N floats;
- * r, r_out: 3N floats. */
+ * r, r_out: 3N floats. ct and m_out (both NULL, or both N floats): the
+ * Sec. 2.1 warp of the next iteration, m_out = trilinear(ct, x + r_out(x)),
+ * made inside the z pass as disc_iterate does. */
 int disc_step_force_smooth(const float* m_dev, const float* f_dev, const float* r_dev,
                            int nx, int ny, int nz, float sigma, float diff_floor, int force_mode,
-                           float* q_dev, float* r_out_dev, float* rt_dev, void* stream);
+                           float* q_dev, float* r_out_dev, float* rt_dev, const float* ct_dev,
+                           float* m_out_dev, void* stream);
 
 /* Algorithm A1 step 6 alone: separable Gaussian of each field component,
  * taps exp(-k^2 / 2 sigma^2) for |k| <= ceil(3 sigma), normalised, indices

@@ -449,3 +449,42 @@ def a_median(ct, s, patch, tau=1e-2):
     s, ps = _d(s)
     nx, ny, nz = _dims(ct)
     return lib().orc_a_median(pc, ps, nx, ny, nz, int(patch[0]), int(patch[1]), int(patch[2]), float(tau))
+
+
+def register_steps(ct, cbct, params, chunk=10, on_chunk=None):
+    """Algorithm A1 (Sec. 2.3) with fixed iteration counts, run from the same
+    C steps as ``register`` but in chunks of ``chunk`` iterations, so a
+    caller can follow a long run: ``on_chunk(level, k, r, f)`` is called
+    after every chunk with the level's iteration count k and the current
+    field and corrected image. The order of operations is that of
+    ``register`` (shift, pyramid, per-level static moments, iterations,
+    up-sampling), so the result is bitwise the same."""
+    if params.mask_mode != 0 or params.stop_eps > 0.0:
+        raise ValueError("register_steps covers the fixed-count, unmasked schedule")
+    ct = np.ascontiguousarray(ct, dtype=np.float64)
+    cb = np.ascontiguousarray(cbct, dtype=np.float64)
+    if params.global_shift:
+        _, s = global_shift(ct, cb)
+    else:
+        s = cb.copy()
+    L = int(params.levels)
+    cts, ss = [ct], [s]
+    for _ in range(L - 1):
+        cts.insert(0, downsample2(cts[0]))
+        ss.insert(0, downsample2(ss[0]))
+    r = np.zeros((3,) + cts[0].shape)
+    f = None
+    for l in range(L):
+        if l > 0:
+            r = upsample_field(r, cts[l].shape)
+        patch = tuple(int(params.patch[d]) for d in range(3))
+        mu_s, var_s = patch_moments(ss[l], patch)
+        f = ss[l].copy()
+        k = 0
+        while k < int(params.iters[l]):
+            n = min(int(chunk), int(params.iters[l]) - k)
+            r, _, f, _ = iterate(cts[l], ss[l], r, params, n=n, mu_s=mu_s, var_s=var_s)
+            k += n
+            if on_chunk is not None:
+                on_chunk(l, k, r, f)
+    return r, f

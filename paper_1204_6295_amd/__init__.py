@@ -77,7 +77,8 @@ _SIGS = [
     ("disc_step_warp", _I, [_V, _V, _I, _I, _I, _V, _V]),
     ("disc_step_static_stats", _I, [_V, _I, _I, _I, _IP, _F, _V, _V]),
     ("disc_step_correct", _I, [_V, _V, _I, _I, _I, _IP, _V, _V]),
-    ("disc_step_force_smooth", _I, [_V, _V, _V, _I, _I, _I, _F, _F, _I, _V, _V, _V, _V]),
+    ("disc_step_force_smooth", _I, [_V, _V, _V, _I, _I, _I, _F, _F, _I, _V, _V, _V, _V, _V, _V]),
+    ("disc_get_mask", _I, [_V, _V, _V]),
     ("disc_get_stats", _I, [_V, _I, _IP, ctypes.POINTER(ctypes.c_double), _I, _V]),
     ("disc_get_mask_params", _I, [_V, ctypes.POINTER(ctypes.c_float), _V]),
     ("disc_step_smooth", _I, [_V, _I, _I, _I, _F, _V, _V, _V]),
@@ -276,6 +277,14 @@ class Registration:
         _check(lib().disc_get_mask_params(self._h, out, _stream(stream)), self._h)
         return dict(zip(("hu0", "a_min", "a_max", "h", "a_m"), [float(v) for v in out]))
 
+    def mask(self, stream=None):
+        """Mask mode: uint8 map of the latest iteration (0 = not masked,
+        p = filled by fill pass p, 255 = masked and never filled)."""
+        _, _, shape = self.state()
+        out = torch.empty(shape, dtype=torch.uint8, device=self.device)
+        _check(lib().disc_get_mask(self._h, _V(out.data_ptr()), _stream(stream)), self._h)
+        return out
+
     def timing_enable(self, max_records):
         _check(lib().disc_timing_enable(self._h, int(max_records)), self._h)
 
@@ -320,18 +329,24 @@ def correct(m, ys, patch, stream=None):
     return f
 
 
-def force_smooth(m, f, r, sigma, diff_floor=1e-3, want_rt=False, force_mode=0, stream=None):
+def force_smooth(m, f, r, sigma, diff_floor=1e-3, want_rt=False, force_mode=0, ct=None, stream=None):
     """Eq. 1 force (static-gradient term, or both terms with force_mode=1),
-    update and Gaussian. Returns r_out, or (r_out, r - u)."""
+    update and Gaussian. Returns r_out, or (r_out, r - u); with ct given,
+    the z pass also warps ct by r_out (the next iteration's m, as in a
+    registration) and m_next is appended to the result."""
     nx, ny, nz = _vol_dims(m)
     q = torch.empty_like(r)
     out = torch.empty_like(r)
     rt = torch.empty_like(r) if want_rt else None
+    m_next = torch.empty_like(m) if ct is not None else None
     _check(lib().disc_step_force_smooth(_dev(m, name="m"), _dev(f, m.shape, "f"),
                                         _dev(r, (3,) + tuple(m.shape), "r"), nx, ny, nz, float(sigma),
                                         float(diff_floor), int(force_mode), _dev(q), _dev(out),
-                                        _dev(rt) if want_rt else None, _stream(stream)))
-    return (out, rt) if want_rt else out
+                                        _dev(rt) if want_rt else None,
+                                        _dev(ct, m.shape, "ct") if ct is not None else None,
+                                        _dev(m_next) if ct is not None else None, _stream(stream)))
+    res = (out,) + ((rt,) if want_rt else ()) + ((m_next,) if ct is not None else ())
+    return res[0] if len(res) == 1 else res
 
 
 def smooth(rt, sigma, stream=None):

@@ -560,6 +560,18 @@ int disc_get_corrected(disc_ctx* c, float* out_dev, void* stream)
     return DISC_OK;
 }
 
+int disc_get_mask(disc_ctx* c, unsigned char* out_dev, void* stream)
+{
+    if (!c) return fail(nullptr, DISC_EINVAL, "context is NULL");
+    if (!c->ready) return fail(c, DISC_ESTATE, "disc_set_volumes has not succeeded");
+    if (!out_dev) return fail(c, DISC_EINVAL, "out is NULL");
+    if (c->p.mask_mode != 1) return fail(c, DISC_ENOTSUP, "mask_mode is 0");
+    if (!c->f_valid) return fail(c, DISC_ESTATE, "no iteration has run at the current level");
+    const Dims d = c->dims[c->level];
+    hipError_t e = hipMemcpyAsync(out_dev, c->stamp, (size_t)d.n(), hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? DISC_OK : hip_fail(c, e, "copy mask");
+}
+
 // ---- single steps -----------------------------------------------------------
 
 #define DISC_CHECK_DIMS(nx, ny, nz)                                                        \
@@ -602,10 +614,13 @@ int disc_step_correct(const float* m_dev, const float* ys_dev, int nx, int ny, i
 
 int disc_step_force_smooth(const float* m_dev, const float* f_dev, const float* r_dev, int nx,
                            int ny, int nz, float sigma, float diff_floor, int force_mode, float* q_dev,
-                           float* r_out_dev, float* rt_dev, void* stream)
+                           float* r_out_dev, float* rt_dev, const float* ct_dev, float* m_out_dev,
+                           void* stream)
 {
     if (!m_dev || !f_dev || !r_dev || !q_dev || !r_out_dev)
         return fail(nullptr, DISC_EINVAL, "null pointer");
+    if ((ct_dev == nullptr) != (m_out_dev == nullptr))
+        return fail(nullptr, DISC_EINVAL, "ct and m_out are both given or both NULL");
     DISC_CHECK_DIMS(nx, ny, nz);
     if (!(diff_floor >= 0.0f) || !std::isfinite(diff_floor))
         return fail(nullptr, DISC_EINVAL, "diff_floor must be finite and >= 0");
@@ -616,7 +631,8 @@ int disc_step_force_smooth(const float* m_dev, const float* f_dev, const float* 
     hipError_t e = disc::launch_force_xy(m_dev, f_dev, r_dev, q_dev, rt_dev, d, diff_floor, force_mode, t,
                                          nullptr,
                                          (hipStream_t)stream);
-    if (e == hipSuccess) e = disc::launch_smooth_z(q_dev, r_out_dev, d, t, nullptr, nullptr, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = disc::launch_smooth_z(q_dev, r_out_dev, d, t, nullptr, nullptr, (hipStream_t)stream, ct_dev, m_out_dev);
     return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "force + smoothing");
 }
 

@@ -150,11 +150,14 @@ def test_step_argument_errors_without_gpu(disc):
     assert L.disc_step_correct(fake, fake, 4, 4, 4, bad, fake, None) == disc.DISC_EINVAL
     assert L.disc_step_static_stats(fake, 4, 4, 4, patch, -1.0, fake, None) == disc.DISC_EINVAL
     assert L.disc_step_force_smooth(fake, fake, fake, 4, 4, 4, 2.0, float("inf"), 0, fake, fake, None,
-                                    None) == disc.DISC_EINVAL
+                                    None, None, None) == disc.DISC_EINVAL
     assert L.disc_step_force_smooth(fake, fake, fake, 4, 4, 4, 2.0, 1e-3, 0, None, fake, None,
-                                    None) == disc.DISC_EINVAL
+                                    None, None, None) == disc.DISC_EINVAL
     assert L.disc_step_force_smooth(fake, fake, fake, 4, 4, 4, 2.0, 1e-3, 2, fake, fake, None,
-                                    None) == disc.DISC_EINVAL
+                                    None, None, None) == disc.DISC_EINVAL
+    # the next iteration's warp needs both the CT and the output
+    assert L.disc_step_force_smooth(fake, fake, fake, 4, 4, 4, 2.0, 1e-3, 0, fake, fake, None,
+                                    fake, None, None) == disc.DISC_EINVAL
     assert L.disc_step_smooth(fake, 4, 4, 4, 3.0, fake, fake, None) == disc.DISC_EINVAL
     assert L.disc_step_shift(fake, fake, 0, fake, None, fake, 1 << 20, None) == disc.DISC_EINVAL
     assert L.disc_step_shift(fake, fake, 10, fake, None, fake, 8, None) == disc.DISC_ENOMEM

@@ -730,3 +730,21 @@ def test_mask_off_limits_and_identical_images():
     assert np.array_equal(r0, r1) and np.array_equal(f0, f1)
     r2, f2 = oracle.register(ct, ct.copy(), oracle.make_params(mask_mode=1, **base))
     assert np.abs(r2).max() == 0.0
+
+
+def test_chunked_schedule_equals_register():
+    """oracle.register_steps (the schedule in chunks, for long runs that
+    report progress) runs the same C steps in the same order as
+    orc_register: bitwise equal field and corrected image, and every chunk
+    reported once per level in order."""
+    g = rng(41)
+    shape = (11, 14, 17)
+    ct = ndi.gaussian_filter(g.normal(size=shape), 1.0) * 900 + 50
+    s0 = 0.9 * ndi.shift(ct, (0.3, 0.6, -0.4), order=1, mode="nearest") + 70 + g.normal(size=shape) * 10
+    p = oracle.make_params(patch=(3, 3, 5), sigma=1.2, levels=2, iters=(5, 7))
+    seen = []
+    rs, fs = oracle.register_steps(ct, s0, p, chunk=3, on_chunk=lambda l, k, r, f: seen.append((l, k)))
+    ro, fo = oracle.register(ct, s0, p)
+    assert seen == [(0, 3), (0, 5), (1, 3), (1, 6), (1, 7)]
+    assert np.abs(ro).max() > 0.05
+    assert np.array_equal(rs, ro) and np.array_equal(fs, fo)
