@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.helpers import STEP_RTOL, rel_err, to_dev, to_np
+from tests.helpers import FIELD_MAX, FIELD_RMS, STEP_RTOL, field_err, rel_err, to_dev, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
@@ -88,7 +88,19 @@ def test_steps_whole_volume(disc, mid_state):
 def test_registration_iterations_whole_volume(disc, case, mid_state):
     """Two iterations of disc_iterate itself from the mid-registration field
     (the second one uses the m made by the first one's z pass), against two
-    oracle iterations from the same FP32 state."""
+    oracle iterations from the same FP32 state.
+
+    The steps match at about 1e-7 on identical inputs (above), but here the
+    oracle keeps m and I'_s in FP64 while the GPU stores them in FP32. Where
+    the two images agree to a fraction of an HU and the gradient of I'_s is
+    as small, the Eq. 1 force is ill-conditioned in d = m - I'_s: with |d|
+    and |grad| near eps_d = 1e-3 HU, the FP32 rounding of m and I'_s (at
+    most 1.2e-4 HU below 2048 HU) moves u by up to about 0.06 voxel at that
+    voxel, and the sigma-2 Gaussian (peak weight 0.0079) spreads it as at
+    most about 5e-4 voxel of field. So the corrected image is held to the
+    per-step bar, the field to 1e-3 voxel after one iteration and to the
+    final-field bars after two (where the first iteration's difference has
+    gone through the warp)."""
     st = mid_state
     reg = disc.Registration(patch=st["patch"], sigma=st["sigma"], levels=1, iters=(2,))
     reg.set_volumes(st["ct"], st["cb"])
@@ -104,8 +116,11 @@ def test_registration_iterations_whole_volume(disc, case, mid_state):
         e_r = max(rel_err(r_g[c], r_ref[c]) for c in range(3))
         e_abs = float(np.abs(r_g - r_ref).max())
         e_f = rel_err(f_g, f_ref)
-        print("iteration %d: field rel %.2g (abs %.2g vox), corrected rel %.2g" % (k + 1, e_r, e_abs, e_f))
-        assert e_r <= STEP_RTOL and e_f <= STEP_RTOL
+        emax, erms = field_err(r_g, r_ref)
+        print("iteration %d: field rel %.2g (abs %.2g vox; per-voxel max %.2g rms %.2g), corrected rel %.2g"
+              % (k + 1, e_r, e_abs, emax, erms, e_f))
+        assert e_f <= STEP_RTOL
+        assert emax <= (1e-3 if k == 0 else FIELD_MAX) and erms <= FIELD_RMS
 
 
 def test_masked_iteration_whole_volume(disc, case):
