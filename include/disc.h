@@ -251,6 +251,19 @@ int disc_ssd_grad(const float* ct_dev, const float* ys_dev, const float* r_dev, 
                   const int patch[3], const float* scale_dev, float* grad_dev, double* loss_dev,
                   void* scratch_dev, size_t scratch_bytes, void* stream);
 
+/* Allocation-free variant of disc_ssd_loss, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same loss from the same kernels,
+ * with the scratch (m, N floats, and the loss partials) in a fixed 32 MiB
+ * device array that every GPU the library runs on holds until the process
+ * ends. No device memory is allocated or freed by this call. Volumes whose
+ * scratch exceeds 32 MiB (about 8.3 million voxels) return DISC_ENOMEM.
+ * The array is shared by every call on one GPU: calls that overlap on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller. Runs on the current device; the stream must belong to it. */
+int disc_ssd_loss_noalloc(const float* ct_dev, const float* ys_dev, const float* r_dev, int nx, int ny,
+                          int nz, const int patch[3], double* loss_dev, void* stream);
+
 /* ---- batches of volumes ------------------------------------------------- */
 /* Many independent CT/CBCT pairs of uneven sizes advanced together, one
  * resolution level, same parameters (Sec. 2.2-2.3 per pair, exactly as

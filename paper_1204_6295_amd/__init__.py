@@ -89,6 +89,7 @@ _SIGS = [
     ("disc_ssd_scratch_bytes", ctypes.c_size_t, [_I, _I, _I]),
     ("disc_ssd_loss", _I, [_V, _V, _V, _I, _I, _I, _IP, _V, _V, ctypes.c_size_t, _V]),
     ("disc_ssd_grad", _I, [_V, _V, _V, _I, _I, _I, _IP, _V, _V, _V, _V, ctypes.c_size_t, _V]),
+    ("disc_ssd_loss_noalloc", _I, [_V, _V, _V, _I, _I, _I, _IP, _V, _V]),
     ("disc_batch_create", _I, [ctypes.POINTER(Params), _I, _IP, ctypes.POINTER(_V)]),
     ("disc_batch_destroy", None, [_V]),
     ("disc_batch_last_error", ctypes.c_char_p, [_V]),
@@ -410,6 +411,19 @@ def ssd_loss(ct, ys, r, patch, stream=None):
     _check(lib().disc_ssd_loss(_dev(ct, name="ct"), _dev(ys, ct.shape, "ys"), _dev(r, (3,) + tuple(ct.shape), "r"),
                                nx, ny, nz, _patch(patch), _V(loss.data_ptr()), _V(scratch.data_ptr()), nb,
                                _stream(stream)))
+    return loss
+
+
+def ssd_loss_noalloc(ct, ys, r, patch, out=None, stream=None):
+    """ssd_loss without device allocation in the library (its scratch is a
+    fixed device array; out: an optional preallocated float64 0-d tensor)."""
+    nx, ny, nz = _vol_dims(ct)
+    loss = out if out is not None else torch.empty((), dtype=torch.float64, device=ct.device)
+    if loss.dtype != torch.float64 or loss.numel() != 1 or not loss.is_cuda:
+        raise TypeError("out must be a one-element float64 device tensor")
+    _check(lib().disc_ssd_loss_noalloc(_dev(ct, name="ct"), _dev(ys, ct.shape, "ys"),
+                                       _dev(r, (3,) + tuple(ct.shape), "r"), nx, ny, nz, _patch(patch),
+                                       _V(loss.data_ptr()), _stream(stream)))
     return loss
 
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -808,6 +809,77 @@ int disc_ssd_grad(const float* ct_dev, const float* ys_dev, const float* r_dev, 
     if (e == hipSuccess && loss_dev)
         e = disc::launch_ssd_finish(s.partial, disc::ssd_partial_count(d), loss_dev, st);
     return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "ssd gradient");
+}
+
+}  // extern "C"
+
+// ---- allocation-free SSD loss ------------------------------------------------
+// The scratch of disc_ssd_loss_noalloc (m and the per-workgroup loss
+// partials) is this fixed device array: every GPU the library runs on holds
+// its own copy until the process ends. Host code never passes the array's
+// name to a kernel (on the host it only stands for the symbol); it uses the
+// device address hipGetSymbolAddress returns, looked up once per device.
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (current device).
+int noalloc_scratch(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, DISC_ENOTSUP, "device %d: the allocation-free loss supports devices 0..%d", dev,
+                    kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(nullptr, DISC_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DISC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int disc_ssd_loss_noalloc(const float* ct_dev, const float* ys_dev, const float* r_dev, int nx, int ny, int nz,
+                          const int patch[3], double* loss_dev, void* stream)
+{
+    if (!ct_dev || !ys_dev || !r_dev || !patch || !loss_dev) return fail(nullptr, DISC_EINVAL, "null pointer");
+    DISC_CHECK_DIMS(nx, ny, nz);
+    if (!valid_patch(patch)) return fail(nullptr, DISC_EINVAL, "invalid patch");
+    const Dims d{nx, ny, nz};
+    // the loss uses the warped image m and the loss partials of the scratch
+    const size_t m_bytes = ((size_t)d.n() * sizeof(float) + 255) & ~(size_t)255;
+    const size_t need = m_bytes + (size_t)disc::ssd_partial_count(d) * sizeof(double);
+    if (need > kNoAllocScratchBytes)
+        return fail(nullptr, DISC_ENOMEM,
+                    "volume of %ld voxels needs %zu bytes of scratch; the allocation-free loss holds %zu "
+                    "(use disc_ssd_loss with a caller workspace)",
+                    d.n(), need, kNoAllocScratchBytes);
+    void* base = nullptr;
+    int rc = noalloc_scratch(&base);
+    if (rc != DISC_OK) return rc;
+    float* m = static_cast<float*>(base);
+    double* partial = reinterpret_cast<double*>(static_cast<char*>(base) + m_bytes);
+    const hipStream_t st = (hipStream_t)stream;
+    // every scratch element read below is written first by this call (m by
+    // the warp, one partial per workgroup by the sweep): nothing is cleared
+    hipError_t e = disc::launch_warp(ct_dev, r_dev, m, d, st);
+    if (e == hipSuccess) e = disc::launch_ssd_moments(m, ys_dev, nullptr, nullptr, partial, d, patch, st);
+    if (e == hipSuccess) e = disc::launch_ssd_finish(partial, disc::ssd_partial_count(d), loss_dev, st);
+    return e == hipSuccess ? DISC_OK : hip_fail(nullptr, e, "ssd loss (allocation-free)");
 }
 
 int disc_copy_kernel(const void* src_dev, void* dst_dev, size_t bytes, void* stream)
