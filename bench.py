@@ -82,7 +82,7 @@ def _ms_per_call(fn, reps, warm=2):
     return (time.perf_counter() - t0) * 1000.0 / reps
 
 
-def finest_level_rate(reg, ct, cb, cfg, reps=3):
+def finest_level_rate(reg, ct, cb, cfg, reps=5):
     """Wall time of the finest level's iterations alone (the coarse levels
     and the set-up run first, untimed); median of reps runs."""
     import torch
@@ -179,8 +179,11 @@ def batched_rate(disc, n_pairs=16, iters=100):
 
     ms_eager = _ms_per_call(run(False), reps=1, warm=1)
     ms_graph = _ms_per_call(run(True), reps=2, warm=1)
-    # batched result against the single-volume path, first pair
+    # batched result against the single-volume path, first pair (same
+    # kernels and arithmetic; only launch knobs differ)
     fe = (b.field(0) - regs[0].field()).abs().max().item()
+    if not fe <= 0.05:
+        raise RuntimeError("batched pair 0 differs from the single-volume path by %.3g voxel" % fe)
     return {"pairs": n_pairs, "shapes_zyx": [list(s) for s in shapes], "voxels": vox, "iterations": iters,
             "ms_sequential": round(ms_seq, 3), "ms_batched_eager": round(ms_eager, 3),
             "ms_batched_graph": round(ms_graph, 3),
@@ -190,10 +193,22 @@ def batched_rate(disc, n_pairs=16, iters=100):
             "pair0_field_max_diff_vs_single": fe}
 
 
-def cpu_baseline(case, params, budget_s=20.0, max_iters=10):
-    """FP64 oracle on the finest level of the same pair: as many iterations as
-    fit in about budget_s (at least one). Static patch moments are computed
-    beforehand and not timed (the GPU computes them once per registration)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, params, budget_s=10.0, max_iters=10):
+    """FP64 oracle on the finest level of the same pair, from r = 0: as many
+    iterations as fit in about budget_s on all host threads, then one
+    iteration on one thread. Static patch moments are computed beforehand and
+    not timed (the GPU computes them once per registration)."""
     import numpy as np
 
     import oracle
@@ -203,25 +218,80 @@ def cpu_baseline(case, params, budget_s=20.0, max_iters=10):
     p = oracle.make_params(patch=params["patch"], sigma=params["sigma"], levels=1,
                            iters=(1,))
     mu_s, var_s = oracle.patch_moments(s, params["patch"])
-    r = np.zeros((3,) + ct.shape)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        r, _, _, _ = oracle.iterate(ct, s, r, p, n=1, mu_s=mu_s, var_s=var_s)
-        n += 1
-        el = time.perf_counter() - t0
-        log("  oracle iteration %d: %.1f s" % (n, el))
-        if n >= max_iters or el * (n + 1) / n > budget_s:
-            break
-    vox = float(ct.size) * n
+    all_threads = oracle.threads()
+
+    def timed(threads, limit):
+        oracle.set_threads(threads)
+        r = np.zeros((3,) + ct.shape)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            r, _, _, _ = oracle.iterate(ct, s, r, p, n=1, mu_s=mu_s, var_s=var_s)
+            n += 1
+            el = time.perf_counter() - t0
+            log("  oracle, %d thread(s), iteration %d: %.1f s" % (threads, n, el))
+            if n >= limit or el * (n + 1) / n > budget_s:
+                return n, el
+
+    n, el = timed(all_threads, max_iters)
+    n1, el1 = timed(1, 1)
+    oracle.set_threads(all_threads)
+    desc = "finest-level iteration(s) of the %dx%dx%d pair from r = 0, patch %s, sigma %g" % (
+        ct.shape[2], ct.shape[1], ct.shape[0], "x".join(map(str, params["patch"])), params["sigma"])
     return {
-        "value": vox / el,
+        "value": float(ct.size) * n / el,
         "unit": "voxel-iterations/s",
-        "cores": oracle.threads(),
+        "cores": all_threads,
         "kind": "oracle",
-        "sample": "%d finest-level iteration(s) of the %dx%dx%d pair from r = 0, patch %s, sigma %g (%.1f s)"
-                  % (n, ct.shape[2], ct.shape[1], ct.shape[0], "x".join(map(str, params["patch"])),
-                     params["sigma"], el),
+        "sample": "%d %s on %d threads (%.1f s)" % (n, desc, all_threads, el),
+        "one_thread": {"value": float(ct.size) * n1 / el1, "unit": "voxel-iterations/s", "cores": 1,
+                       "sample": "%d %s on 1 thread (%.1f s)" % (n1, desc, el1)},
+        "cpu_model": _cpu_model(),
+        "host_threads_visible": os.cpu_count(),
+    }
+
+
+def workload_summary(disc, name, steps=3):
+    """Another workload of the same registration: whole-registration time,
+    the finest level alone (median of 5) and per-kernel averages at the
+    finest level with their algorithmic GB/s."""
+    import torch
+
+    from synth.phantom import CONFIGS, make_case
+
+    cfg = CONFIGS[name]
+    case = make_case(name, device="cuda")
+    ct = torch.from_numpy(case.ct).cuda()
+    cb = torch.from_numpy(case.cbct).cuda()
+    params = dict(patch=cfg["patch"], sigma=cfg["sigma"], levels=cfg["levels"], iters=cfg["iters"])
+    reg = disc.Registration(**params)
+
+    def step():
+        reg.set_volumes(ct, cb)
+        reg.run()
+
+    ms = _ms_per_call(step, reps=steps, warm=1)
+    fin = finest_level_rate(reg, ct, cb, cfg)
+    reg.timing_enable(4 * sum(cfg["iters"]) + 16)
+    step()
+    torch.cuda.synchronize()
+    kern = {}
+    for kname in disc.KERNELS:
+        n, kms, vox = reg.timing_read(kname, cfg["levels"] - 1)
+        if n:
+            kern[kname] = {"launches": n, "avg_us": round(1000.0 * kms / n, 2),
+                           "gbs": round(BYTES_PER_VOXEL[kname] * vox / (kms * 1e-3) / 1e9, 1)}
+    reg.timing_enable(0)
+    reg.close()
+    n_fin = float(np.prod(cfg["shape"]))
+    return {
+        "shape_zyx": list(cfg["shape"]), "patch": list(cfg["patch"]), "sigma": cfg["sigma"],
+        "levels": cfg["levels"], "iters_per_level": list(cfg["iters"]),
+        "ms_per_registration": round(ms, 3), "finest_level": fin,
+        "finest_level_kernels": kern,
+        "effective_hbm_frac_at_32B": round(ALGORITHMIC_MIN_BYTES * fin["voxel_iterations_per_s"]
+                                           / (HBM_PEAK_GBS * 1e9), 4),
+        "finest_voxels": n_fin,
     }
 
 
@@ -315,11 +385,25 @@ def main():
         n, ms, vox = reg.timing_read(dom, cfg["levels"] - 1)
         avg_s = ms / n * 1e-3
         achieved = BYTES_PER_VOXEL[dom] * (vox / n) / avg_s / 1e9
+        traffic = measured_traffic(dom, args.workload)
+        # the whole finest-level iteration (every kernel of one iteration)
+        it_us = 0.0
+        for name in ("correct", "force_xy", "smooth_z"):
+            nk, msk, _ = reg.timing_read(name, cfg["levels"] - 1)
+            it_us += 1000.0 * msk / nk if nk else 0.0
+        design_b = BYTES_PER_VOXEL["correct"] + BYTES_PER_VOXEL["force_xy"] + BYTES_PER_VOXEL["smooth_z"]
         roofline = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, args.workload),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_gbs": round(traffic / avg_s / 1e9, 1) if traffic else None,
             "kernel": dom, "level": "finest", "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
             "bytes_per_voxel": BYTES_PER_VOXEL[dom], "voxels_per_launch": vox / n,
+            "iteration": {
+                "us": round(it_us, 2), "design_bytes_per_voxel": design_b,
+                "design_frac": round(design_b * (vox / n) / (it_us * 1e-6) / (HBM_PEAK_GBS * 1e9), 4),
+                "effective_frac_at_32B": round(ALGORITHMIC_MIN_BYTES * (vox / n) / (it_us * 1e-6)
+                                               / (HBM_PEAK_GBS * 1e9), 4),
+            },
         }
         for name, kk in kernels.items():
             log("  %-9s launches %5d  avg %8.2f us  %7.1f GB/s  share %.1f%%" % (
@@ -381,6 +465,17 @@ def main():
             bat["ms_sequential"], bat["ms_batched_eager"], bat["ms_batched_graph"],
             bat["speedup_graph_vs_sequential"], bat["tiles"]))
         out["batched"] = bat
+        others = {}
+        for wname in ("ellipsoid48", "hn512x512x160"):
+            if wname == args.workload:
+                continue
+            log("workload %s" % wname)
+            others[wname] = workload_summary(disc, wname)
+            fl = others[wname]["finest_level"]
+            log("  %.3f ms per registration; finest level %.4f ms per iteration, %.3g voxel-it/s; kernels %s" % (
+                others[wname]["ms_per_registration"], fl["ms_per_iteration"], fl["voxel_iterations_per_s"],
+                others[wname]["finest_level_kernels"]))
+        out["workloads"] = others
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(case, params)

@@ -52,7 +52,8 @@ typedef enum {
     DISC_ENOMEM = -2,   /* workspace smaller than disc_workspace_bytes() */
     DISC_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
     DISC_ESTATE = -4,   /* call out of order (e.g. iterate before set_volumes) */
-    DISC_ENOTSUP = -5   /* valid request outside what the library supports */
+    DISC_ENOTSUP = -5,  /* valid request outside what the library supports */
+    DISC_ENONFINITE = -6 /* an input volume holds NaN or Inf (check_finite = 1) */
 } disc_status;
 
 typedef struct {
@@ -77,13 +78,16 @@ typedef struct {
     int   fill_t[3];     /* region T of Eq. 8-9, odd extents (7, 7, 3), counted inside the volume */
     int   fill_passes;   /* fill passes per iteration, 1..64 (10); a voxel still unfilled keeps
                             its Eq. 5-6 a, b */
+    int   check_finite;  /* 1: disc_set_volumes counts NaN / Inf voxels of ct and cbct first and
+                            returns DISC_ENONFINITE if there are any (synchronises the stream);
+                            0 (default): inputs are trusted */
 } disc_params;
 
 /* Defaults: patch 11^3, sigma 2, 3 levels x 100 iterations, global shift on,
  * tau = 1e-2 HU^2, eps_d = 1e-3 HU, static-gradient force, fixed counts
  * (stop_eps = 0, stop_lag = 10), no mask (mask_mode 0; its settings default
  * to the Sec. 2.3 rules: hu0 0 = 2 Delta HU, a range 0.5..1.5 a_m, h = HU_0,
- * T = 7x7x3, 10 passes). */
+ * T = 7x7x3, 10 passes), no finite check of the inputs. */
 int disc_params_default(disc_params* p);
 
 /* Validates *p and creates a host-side context. Does not touch the GPU.
@@ -106,7 +110,11 @@ size_t disc_workspace_bytes(const disc_params* p, int nx, int ny, int nz);
  * level (fixed for the whole run, Sec. 2.2 corrects the original I_s), and
  * r := 0 at the coarsest level. ct_dev is borrowed (read every iteration at
  * the finest level) until the next set_volumes or destroy; cbct_dev is only
- * read by this call. workspace_dev (256-byte aligned) is borrowed likewise. */
+ * read by this call. workspace_dev (256-byte aligned) is borrowed likewise.
+ * Volumes are in voxel units: the method needs no voxel spacing (the field,
+ * the patch and sigma are all in voxels). With check_finite = 1 a NaN or Inf
+ * in ct or cbct returns DISC_ENONFINITE before any other device work (the
+ * context is then not ready). */
 int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev,
                      int nx, int ny, int nz, void* workspace_dev,
                      size_t workspace_bytes, void* stream);
@@ -267,9 +275,11 @@ int disc_ssd_loss_noalloc(const float* ct_dev, const float* ys_dev, const float*
 /* ---- batches of volumes ------------------------------------------------- */
 /* Many independent CT/CBCT pairs of uneven sizes advanced together, one
  * resolution level, same parameters (Sec. 2.2-2.3 per pair, exactly as
- * disc_iterate with levels = 1). Each iteration of the whole batch is four
- * launches (warp; moments + correction; force + xy smoothing; z smoothing),
- * each covering the workgroups of every volume; with use_graph = 1 the n
+ * disc_iterate with levels = 1). Each iteration of the whole batch is three
+ * launches (moments + correction; force + xy smoothing; z smoothing, which
+ * also warps the CT for the next iteration; the standalone warp runs once
+ * after set_volumes), each covering the workgroups of every volume; with
+ * use_graph = 1 the n
  * iterations are captured once into a HIP graph (on an internal stream) and
  * replayed on `stream` by later calls with the same n.
  *

@@ -100,6 +100,8 @@ def lib():
         L = ctypes.CDLL(_SO)
         L.orc_threads.restype = ctypes.c_int
         L.orc_threads.argtypes = []
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_mean.restype = ctypes.c_double
         L.orc_mean.argtypes = [_D, ctypes.c_long]
         L.orc_global_shift.restype = ctypes.c_double
@@ -159,6 +161,11 @@ def _dims(v):
 
 def threads():
     return int(lib().orc_threads())
+
+
+def set_threads(n):
+    """OpenMP threads of later oracle calls (n >= 1)."""
+    lib().orc_set_threads(int(n))
 
 
 def mean(v):

@@ -42,6 +42,13 @@ int orc_threads(void)
     return omp_get_max_threads();
 }
 
+/* Number of OpenMP threads of later calls (n >= 1); for timing the oracle
+ * at one thread and at all host threads. */
+void orc_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+}
+
 static int clampi(int v, int n)
 {
     if (v < 0) return 0;

@@ -50,6 +50,7 @@ typedef struct {
 
 /* Number of OpenMP threads the whole-volume functions use. */
 int orc_threads(void);
+void orc_set_threads(int n);
 
 /* Sec. 2.3: plain mean over all voxels. */
 double orc_mean(const double* v, long n);

@@ -18,7 +18,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdisc.so")
 
-DISC_OK, DISC_EINVAL, DISC_ENOMEM, DISC_EHIP, DISC_ESTATE, DISC_ENOTSUP = 0, -1, -2, -3, -4, -5
+DISC_OK, DISC_EINVAL, DISC_ENOMEM, DISC_EHIP, DISC_ESTATE, DISC_ENOTSUP, DISC_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MAX_LEVELS = 8
 KERNELS = {"warp": 0, "correct": 1, "force_xy": 2, "smooth_z": 3, "upsample": 4, "fill": 5}
 
@@ -49,6 +49,7 @@ class Params(ctypes.Structure):
         ("fill_h", ctypes.c_float),
         ("fill_t", ctypes.c_int * 3),
         ("fill_passes", ctypes.c_int),
+        ("check_finite", ctypes.c_int),
     ]
 
 
@@ -157,7 +158,7 @@ def _vol_dims(t):
 
 def make_params(patch=(11, 11, 11), sigma=2.0, levels=3, iters=(100, 100, 100), global_shift=True,
                 var_floor=1e-2, diff_floor=1e-3, force_mode=0, stop_eps=0.0, stop_lag=10, mask_mode=0,
-                hu0=0.0, a_lo=0.5, a_hi=1.5, fill_h=0.0, fill_t=(7, 7, 3), fill_passes=10):
+                hu0=0.0, a_lo=0.5, a_hi=1.5, fill_h=0.0, fill_t=(7, 7, 3), fill_passes=10, check_finite=False):
     p = Params()
     lib().disc_params_default(ctypes.byref(p))
     for d in range(3):
@@ -183,6 +184,7 @@ def make_params(patch=(11, 11, 11), sigma=2.0, levels=3, iters=(100, 100, 100), 
     for d in range(3):
         p.fill_t[d] = int(fill_t[d])
     p.fill_passes = int(fill_passes)
+    p.check_finite = 1 if check_finite else 0
     return p
 
 
@@ -196,10 +198,10 @@ class Registration:
     def __init__(self, patch=(11, 11, 11), sigma=2.0, levels=3, iters=(100, 100, 100),
                  global_shift=True, var_floor=1e-2, diff_floor=1e-3, force_mode=0, stop_eps=0.0,
                  stop_lag=10, mask_mode=0, hu0=0.0, a_lo=0.5, a_hi=1.5, fill_h=0.0, fill_t=(7, 7, 3),
-                 fill_passes=10):
+                 fill_passes=10, check_finite=False):
         self.params = make_params(patch, sigma, levels, iters, global_shift, var_floor, diff_floor,
                                   force_mode, stop_eps, stop_lag, mask_mode, hu0, a_lo, a_hi, fill_h, fill_t,
-                                  fill_passes)
+                                  fill_passes, check_finite)
         h = _V()
         _check(lib().disc_create(ctypes.byref(self.params), ctypes.byref(h)))
         self._h = h

@@ -148,6 +148,7 @@ int check_params(disc_ctx* c, const disc_params* p)
         if (p->fill_passes < 1 || p->fill_passes > 64)
             return fail(c, DISC_EINVAL, "fill_passes must be in 1..64");
     }
+    if (p->check_finite != 0 && p->check_finite != 1) return fail(c, DISC_EINVAL, "check_finite must be 0 or 1");
     return DISC_OK;
 }
 
@@ -436,6 +437,19 @@ int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev, in
     const Dims fin = c->dims[L - 1];
     c->ct[L - 1] = ct_dev;
     hipError_t e;
+    if (c->p.check_finite) {
+        // count NaN / Inf voxels into the first word of the shift scratch
+        // (the shift below overwrites it) and wait for the answer
+        int* cnt = static_cast<int*>(c->scratch);
+        int host_cnt = 0;
+        e = disc::launch_fill(reinterpret_cast<float*>(cnt), 1, 0.0f, st);
+        if (e == hipSuccess) e = disc::launch_count_nonfinite(ct_dev, cbct_dev, fin.n(), cnt, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&host_cnt, cnt, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "finite check");
+        if (host_cnt > 0)
+            return fail(c, DISC_ENONFINITE, "ct and cbct hold %d NaN or Inf voxels", host_cnt);
+    }
     const bool mask = c->p.mask_mode == 1;
     if (c->p.global_shift) {
         e = disc::launch_shift(ct_dev, cbct_dev, fin.n(), c->s[L - 1], mask ? c->dhu : nullptr, c->scratch, st);

@@ -113,6 +113,8 @@ hipError_t launch_shift(const float* ct, const float* cbct, long n, float* s, do
 hipError_t launch_downsample(const float* in, float* out, Dims d, hipStream_t st);
 hipError_t launch_upsample_field(const float* rc, Dims dc, float* rf, Dims df, hipStream_t st);
 hipError_t launch_fill(float* p, long n, float v, hipStream_t st);
+// *count += number of NaN / Inf values in a[0..n) and b[0..n).
+hipError_t launch_count_nonfinite(const float* a, const float* b, long n, int* count, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 
 // Launch knobs of a batched iteration (chosen by the autotuner).

@@ -134,6 +134,20 @@ __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, long n, flo
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) p[i] = v;
 }
 
+// Number of NaN / Inf values (exponent bits all set) in a and b: one
+// atomic add per wave of its ballot count.
+__global__ __launch_bounds__(256) void k_count_nonfinite(const unsigned* __restrict__ a,
+                                                         const unsigned* __restrict__ b, long n,
+                                                         int* __restrict__ count)
+{
+    int bad = 0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+        bad += ((a[i] & 0x7f800000u) == 0x7f800000u) + ((b[i] & 0x7f800000u) == 0x7f800000u);
+    // wave sum of the per-lane counts
+    for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off, 64);
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
+}
+
 __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src,
                                               float4* __restrict__ dst, long n16)
 {
@@ -274,6 +288,13 @@ hipError_t launch_upsample_field(const float* rc, Dims dc, float* rf, Dims df, h
 hipError_t launch_fill(float* p, long n, float v, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256 * 8)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const float* a, const float* b, long n, int* count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks_for(n, 256 * 8)), dim3(256), 0, s,
+                       reinterpret_cast<const unsigned*>(a), reinterpret_cast<const unsigned*>(b), n, count);
     return hipGetLastError();
 }
 

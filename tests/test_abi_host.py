@@ -41,8 +41,8 @@ def test_every_declared_symbol_is_exported(disc):
 
 def test_params_struct_layout(disc):
     # int[3], float, int, int[8], int, float, float, int, float, int,
-    # int, float, float, float, float, int[3], int
-    assert ctypes.sizeof(disc.Params) == 4 * (3 + 1 + 1 + 8 + 1 + 1 + 1 + 1 + 1 + 1 + 1 + 4 + 3 + 1)
+    # int, float, float, float, float, int[3], int, int
+    assert ctypes.sizeof(disc.Params) == 4 * (3 + 1 + 1 + 8 + 1 + 1 + 1 + 1 + 1 + 1 + 1 + 4 + 3 + 1 + 1)
 
 
 def test_defaults(disc):

@@ -126,3 +126,22 @@ def test_state_machine_and_errors(disc):
     assert np.array_equal(to_np(reg.field()), r_a)
     with pytest.raises(ValueError):
         reg.set_field(torch.zeros((3, 4, 4, 4), device="cuda:0"))
+
+
+def test_check_finite_rejects_nan_and_inf_inputs(disc):
+    """check_finite = 1: NaN / Inf voxels in the inputs are counted on the
+    device and set-up returns DISC_ENONFINITE; finite inputs run as usual
+    (identical images keep the field exactly zero)."""
+    g = np.random.default_rng([5, 1])
+    ct = (g.normal(size=(20, 24, 70)) * 300).astype(np.float32)
+    cb = ct.copy()
+    cb[3, 4, 5] = np.nan
+    ct[19, 23, 69] = -np.inf
+    reg = disc.Registration(patch=(5, 5, 5), sigma=1.5, levels=1, iters=(2,), check_finite=True)
+    with pytest.raises(disc.DiscError) as ei:
+        reg.set_volumes(to_dev(ct), to_dev(cb))
+    assert ei.value.code == disc.DISC_ENONFINITE and "2 NaN" in str(ei.value)
+    ct[19, 23, 69] = 7.0
+    reg.set_volumes(to_dev(ct), to_dev(ct))
+    reg.run()
+    assert np.array_equal(to_np(reg.field()), np.zeros((3,) + ct.shape, np.float32))
