@@ -118,6 +118,56 @@ def backward_rate(disc, ct, cb, r, cfg, plain_ms_per_it, reps=10):
             "vs_plain_iteration": round(ms_grad / plain_ms_per_it, 3)}
 
 
+def gd_vs_demons(disc, ct, cb, r_true, cfg, steps=200):
+    """Differentiable DISC used as a registration: `steps` gradient-descent
+    steps on the SSD loss, r <- r - eta G_sigma * dL/dr (the gradient smoothed
+    by the same Gaussian that regularises the demons field), against `steps`
+    demons iterations, both at the finest level from r = 0. eta is fixed from
+    the first smoothed gradient so that the largest first update is half a
+    voxel, the bound each demons force obeys. Reported: wall time of each loop
+    and the loss and mean field error (vs the known deformation, inside the
+    body) each reaches."""
+    import torch
+
+    patch, sigma = cfg["patch"], cfg["sigma"]
+    s, _ = disc.shift(ct, cb)
+    ys = disc.static_stats(s, patch)
+    body = ct > -500
+
+    def field_error(r):
+        return ((r - r_true) ** 2).sum(0).sqrt()[body].mean().item()
+
+    r = torch.zeros((3,) + tuple(ct.shape), dtype=torch.float32, device=ct.device)
+    loss0 = disc.ssd_loss(ct, ys, r, patch).item()
+    eta = 0.5 / disc.smooth(disc.ssd_grad(ct, ys, r, patch), sigma).abs().max()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = r - eta * disc.smooth(disc.ssd_grad(ct, ys, r, patch), sigma)
+    torch.cuda.synchronize()
+    ms_gd = (time.perf_counter() - t0) * 1000.0
+    loss_gd = disc.ssd_loss(ct, ys, r, patch).item()
+    err_gd = field_error(r)
+    reg = disc.Registration(patch=patch, sigma=sigma, levels=1, iters=(steps,))
+    reg.set_volumes(ct, cb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reg.run()
+    torch.cuda.synchronize()
+    ms_dm = (time.perf_counter() - t0) * 1000.0
+    rd = reg.field()
+    loss_dm = disc.ssd_loss(ct, ys, rd, patch).item()
+    err_dm = field_error(rd)
+    reg.close()
+    return {"steps": steps, "eta": float(eta),
+            "loss_at_r0": loss0,
+            "gradient_descent": {"ms": round(ms_gd, 3), "loss": loss_gd, "loss_ratio": round(loss_gd / loss0, 5),
+                                 "mean_field_error_body_vox": round(err_gd, 4)},
+            "demons": {"ms": round(ms_dm, 3), "loss": loss_dm, "loss_ratio": round(loss_dm / loss0, 5),
+                       "mean_field_error_body_vox": round(err_dm, 4)},
+            "mean_field_error_body_vox_at_r0": round(field_error(torch.zeros_like(r)), 4)}
+
+
 def variant_rates(disc, ct, cb, cfg, plain_ms, reps=3):
     """The same registration with the method's variants on: both terms of
     Eq. 1, the Eq. 7-10 mask and fill, and the Sec. 2.3 stopping rule
@@ -454,6 +504,14 @@ def main():
         bwd = backward_rate(disc, ct, cb, r_mid, cfg, fin["ms_per_iteration"])
         log("differentiable: loss %.3f ms, loss + gradient %.3f ms (%.2fx a plain iteration)" % (
             bwd["ms_loss"], bwd["ms_loss_and_grad"], bwd["vs_plain_iteration"]))
+        gd = gd_vs_demons(disc, ct, cb, torch.from_numpy(case.r_true).float().to(dev), cfg)
+        log("gradient descent vs demons, %d steps: GD %.1f ms, loss x%.4f, field err %.3f vox; "
+            "demons %.1f ms, loss x%.4f, field err %.3f vox (r = 0: %.3f vox)" % (
+                gd["steps"], gd["gradient_descent"]["ms"], gd["gradient_descent"]["loss_ratio"],
+                gd["gradient_descent"]["mean_field_error_body_vox"], gd["demons"]["ms"],
+                gd["demons"]["loss_ratio"], gd["demons"]["mean_field_error_body_vox"],
+                gd["mean_field_error_body_vox_at_r0"]))
+        bwd["gd_vs_demons"] = gd
         out["backward"] = bwd
         var = variant_rates(disc, ct, cb, cfg, ms_per_step)
         log("variants: " + ", ".join("%s %.2f ms (%.2fx)" % (k, v["ms_per_registration"], v["vs_plain"])

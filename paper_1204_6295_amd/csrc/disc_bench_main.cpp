@@ -9,7 +9,9 @@
 // usage: disc_bench CT.f32 CBCT.f32 NX NY NZ PATCH SIGMA LEVELS ITERS STEPS COPY_MIB [VARIANT]
 //   VARIANT 0 plain (default), 1 Eq. 7-10 mask and fill (default rules,
 //   T = 7x7x3, 10 passes), 2 both Eq. 1 force terms, 3 the Sec. 2.3 stopping
-//   rule (eps 1e-4, lag 10).
+//   rule (eps 1e-4, lag 10), 4 plain registrations followed by STEPS
+//   evaluations of the differentiable path (SSD loss and gradient) at the
+//   registered field.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -62,7 +64,7 @@ int main(int argc, char** argv)
     const int steps = std::atoi(argv[10]);
     const size_t copy_bytes = (size_t)std::atol(argv[11]) << 20;
     if (nx < 1 || ny < 1 || nz < 1 || levels < 1 || levels > DISC_MAX_LEVELS || steps < 0 || variant < 0 ||
-        variant > 3) {
+        variant > 4) {
         std::fprintf(stderr, "invalid sizes\n");
         return 2;
     }
@@ -106,6 +108,37 @@ int main(int argc, char** argv)
     CHECK_HIP(hipStreamSynchronize(st));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     std::printf("registrations: %d in %.3f ms (%.3f ms each)\n", steps, ms, steps ? ms / steps : 0.0);
+
+    if (variant == 4) {
+        // loss + gradient at the registered finest-level field
+        const int pt[3] = {patch, patch, patch};
+        float *d_s = nullptr, *d_ys = nullptr, *d_r = nullptr, *d_g = nullptr;
+        double* d_loss = nullptr;
+        void *d_sc = nullptr, *d_ssc = nullptr;
+        const size_t sc_bytes = disc_ssd_scratch_bytes(nx, ny, nz);
+        const size_t ssc_bytes = disc_step_shift_scratch_bytes();
+        CHECK_HIP(hipMalloc(&d_s, n * sizeof(float)));
+        CHECK_HIP(hipMalloc(&d_ys, n * sizeof(float)));
+        CHECK_HIP(hipMalloc(&d_r, 3 * n * sizeof(float)));
+        CHECK_HIP(hipMalloc(&d_g, 3 * n * sizeof(float)));
+        CHECK_HIP(hipMalloc(&d_loss, sizeof(double)));
+        CHECK_HIP(hipMalloc(&d_sc, sc_bytes));
+        CHECK_HIP(hipMalloc(&d_ssc, ssc_bytes));
+        CHECK_DISC(c, disc_get_field(c, d_r, nullptr, st));
+        CHECK_DISC(nullptr, disc_step_shift(d_ct, d_cb, (long)n, d_s, nullptr, d_ssc, ssc_bytes, st));
+        CHECK_DISC(nullptr, disc_step_static_stats(d_s, nx, ny, nz, pt, p.var_floor, d_ys, st));
+        const auto t1 = std::chrono::steady_clock::now();
+        for (int s = 0; s < steps; ++s)
+            CHECK_DISC(nullptr, disc_ssd_grad(d_ct, d_ys, d_r, nx, ny, nz, pt, nullptr, d_g, d_loss, d_sc, sc_bytes, st));
+        CHECK_HIP(hipStreamSynchronize(st));
+        const double ms1 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+        double loss = 0.0;
+        CHECK_HIP(hipMemcpy(&loss, d_loss, sizeof(double), hipMemcpyDeviceToHost));
+        std::printf("loss + gradient: %d in %.3f ms (%.3f ms each), loss %.6g\n", steps, ms1, steps ? ms1 / steps : 0.0,
+                    loss);
+        for (void* q : {(void*)d_s, (void*)d_ys, (void*)d_r, (void*)d_g, (void*)d_loss, d_sc, d_ssc})
+            CHECK_HIP(hipFree(q));
+    }
 
     if (copy_bytes) {
         void *a = nullptr, *b = nullptr;
