@@ -28,7 +28,7 @@
  *             map to DISC_EHIP. disc_last_error() describes the last failure
  *             (per context, or per thread for the context-free calls).
  *   Threads.  A context is not thread-safe; use one context per stream.
- *   Sizes.    nx, ny, nz >= 1; nx * ny * nz < 2^31. Patch extents are odd,
+ *   Sizes.    nx, ny, nz >= 1; nx * ny * nz < 2^30. Patch extents are odd,
  *             1 <= px, py <= 31 and 1 <= pz <= 15. Gaussian sigma in
  *             (0, 8/3] voxels (at most 17 taps).
  */

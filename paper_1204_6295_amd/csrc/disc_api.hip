@@ -107,7 +107,7 @@ bool valid_patch(const int patch[3])
 bool valid_dims(int nx, int ny, int nz)
 {
     if (nx < 1 || ny < 1 || nz < 1 || nz > 65535) return false;
-    return (long)nx * ny * nz < (1L << 31);
+    return (long)nx * ny * nz < (1L << 30);
 }
 
 int check_params(disc_ctx* c, const disc_params* p)
@@ -423,7 +423,7 @@ int disc_set_volumes(disc_ctx* c, const float* ct_dev, const float* cbct_dev, in
     if (!ct_dev || !cbct_dev || !workspace_dev)
         return fail(c, DISC_EINVAL, "ct, cbct and workspace must be device pointers");
     if (!valid_dims(nx, ny, nz))
-        return fail(c, DISC_EINVAL, "dims (%d,%d,%d): need >= 1, nz <= 65535, N < 2^31", nx, ny, nz);
+        return fail(c, DISC_EINVAL, "dims (%d,%d,%d): need >= 1, nz <= 65535, N < 2^30", nx, ny, nz);
     if (((uintptr_t)workspace_dev & 255) != 0)
         return fail(c, DISC_EINVAL, "workspace must be 256-byte aligned");
     const size_t need = disc_workspace_bytes(&c->p, nx, ny, nz);
@@ -591,7 +591,7 @@ int disc_get_mask(disc_ctx* c, unsigned char* out_dev, void* stream)
 
 #define DISC_CHECK_DIMS(nx, ny, nz)                                                        \
     if (!valid_dims(nx, ny, nz))                                                           \
-        return fail(nullptr, DISC_EINVAL, "dims (%d,%d,%d): need >= 1, nz <= 65535, N < 2^31", \
+        return fail(nullptr, DISC_EINVAL, "dims (%d,%d,%d): need >= 1, nz <= 65535, N < 2^30", \
                     nx, ny, nz)
 
 int disc_step_warp(const float* ct_dev, const float* r_dev, int nx, int ny, int nz, float* m_dev,
@@ -673,7 +673,7 @@ int disc_step_shift(const float* ct_dev, const float* cbct_dev, long n, float* s
                     double* dhu_dev, void* scratch_dev, size_t scratch_bytes, void* stream)
 {
     if (!ct_dev || !cbct_dev || !s_dev || !scratch_dev) return fail(nullptr, DISC_EINVAL, "null pointer");
-    if (n < 1 || n >= (1L << 31)) return fail(nullptr, DISC_EINVAL, "n must be in [1, 2^31)");
+    if (n < 1 || n >= (1L << 30)) return fail(nullptr, DISC_EINVAL, "n must be in [1, 2^30)");
     if (scratch_bytes < disc::shift_scratch_bytes())
         return fail(nullptr, DISC_ENOMEM, "scratch too small");
     if (((uintptr_t)scratch_dev & 15) != 0) return fail(nullptr, DISC_EINVAL, "scratch must be 16-byte aligned");

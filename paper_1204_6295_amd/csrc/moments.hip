@@ -160,16 +160,22 @@ __device__ __forceinline__ void moments_body(const MomArgs& a, const int bid)
         soff[q] = gval[q] ? row * MAXPW + col : 0;
     }
     const int nplanes = (z1 - z0) + 2 * RZ;
+    // buffer access: fixed per-lane byte offsets, the plane a scalar byte
+    // offset (resources are rebuilt where used from the kernel arguments)
+    const long vb = plane * 4 * (long)a.nz;
+    const int pb = (int)plane * 4;
     auto fetch = [&](float(&dst)[NQ], int p) {
-        const float* src = a.img + (long)clampi(z0 - RZ + min(p, nplanes - 1), a.nz) * plane;
+        const Rsrc ib = make_rsrc(a.img, vb);
+        const int so = clampi(z0 - RZ + min(p, nplanes - 1), a.nz) * pb;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) dst[q] = src[goff[q]];
+        for (int q = 0; q < NQ; ++q) dst[q] = ld(ib, goff[q] * 4, so);
     };
     // the epilogue's per-voxel input (ys, or the static image itself) for the
     // output made when plane p enters the window
-    const float* epi = STATIC ? a.img : a.ys_in;
-    const long col_off = (long)min(oy, a.ny - 1) * a.nx + min(ox, a.nx - 1);
-    auto epi_load = [&](int p) { return epi[(long)clampi(z0 + p - 2 * RZ, a.nz) * plane + col_off]; };
+    const int col_off = min(oy, a.ny - 1) * a.nx + min(ox, a.nx - 1);
+    auto epi_load = [&](int p) {
+        return ld(make_rsrc(STATIC ? a.img : a.ys_in, vb), col_off * 4, clampi(z0 + p - 2 * RZ, a.nz) * pb);
+    };
     double loss = 0.0;  // SSD: sum of D^2 over this thread's voxels
 
     // Software pipeline, one barrier per step q:
@@ -305,7 +311,7 @@ __device__ __forceinline__ void moments_body(const MomArgs& a, const int bid)
                     // |I'_s - m| well below eps_d.
                     const float yv = epi_cur;
                     const double c = (__float_as_uint(yv) & 1u) ? 1.0 : (double)sqrtf((float)var);
-                    a.out[idx] = (float)fma(c, (double)yv, mu);
+                    st(make_rsrc(a.out, vb), col_off * 4, oz * pb, (float)fma(c, (double)yv, mu));
                 }
             }
         }

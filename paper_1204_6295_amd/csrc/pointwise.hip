@@ -41,8 +41,9 @@ __device__ inline void warp_body(const float* __restrict__ ct, const float* __re
         ryb = r[N + ib];
         rzb = r[2 * N + ib];
     }
-    const float ma = warp_at(ct, x, ya, z, rxa, rya, rza, nx, ny, nz);
-    if (has_b) m[ib] = warp_at(ct, x, yb, z, rxb, ryb, rzb, nx, ny, nz);
+    const WarpSrc w = warp_src(ct, nx, ny, nz);
+    const float ma = warp_at(w, x, ya, z, rxa, rya, rza);
+    if (has_b) m[ib] = warp_at(w, x, yb, z, rxb, ryb, rzb);
     m[ia] = ma;
 }
 

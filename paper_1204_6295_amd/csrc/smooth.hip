@@ -91,12 +91,9 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
     const int x0 = bx * QTX, y0 = by * QTY;
     const int z0 = bz * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
     const int t = threadIdx.x;
-    // element offsets fit in 32 bits (the ABI bounds N below 2^31)
+    // element offsets fit in 32 bits (the ABI bounds N below 2^30)
     const int plane = a.nx * a.ny;
     const long N = (long)plane * a.nz;
-    const float* r0p = a.r;
-    const float* r1p = a.r + N;
-    const float* r2p = a.r + 2 * N;
 
     // per-thread geometry, fixed over the sweep. Region point q of this
     // thread sits at clamped voxel (gx, gy); its f neighbours are the clamped
@@ -139,6 +136,11 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
     }
 
     const int nplanes = z1 - z0;
+    // buffer access: fixed per-lane byte offsets (region slots), the plane a
+    // scalar byte offset. Resources are rebuilt where used from the kernel
+    // arguments (scalar work the compiler hoists; none is captured by a lambda)
+    const long cb = N * 4;
+    const int pb = plane * 4;
     // registers: the f (and m) region of the next plane; per-point data in two sets
     float pf[NF], pmf[DBL ? NF : 1];
     struct Pt {
@@ -146,33 +148,38 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
     };
     Pt setA, setB;
     auto fetch_region = [&](int p) {  // f (and m) region of plane p (clamped: always valid)
-        const int zoff = (z0 + min(p, nplanes - 1)) * plane;
+        const int so = (z0 + min(p, nplanes - 1)) * pb;
         if (FORCE) {
+            const Rsrc fb = make_rsrc(a.f, cb);
 #pragma unroll
-            for (int q = 0; q < NF; ++q) pf[q] = a.f[zoff + foff[q]];
+            for (int q = 0; q < NF; ++q) pf[q] = ld(fb, foff[q] * 4, so);
         }
         if (DBL) {
+            const Rsrc mb = make_rsrc(a.m, cb);
 #pragma unroll
-            for (int q = 0; q < NF; ++q) pmf[q] = a.m[zoff + foff[q]];
+            for (int q = 0; q < NF; ++q) pmf[q] = ld(mb, foff[q] * 4, so);
         }
     };
     auto fetch_points = [&](Pt& d, int p) {
         const int z = z0 + min(p, nplanes - 1);
-        const int zoff = z * plane;
-        const int zu = clampi(z + 1, a.nz) * plane, zd = clampi(z - 1, a.nz) * plane;
+        const int so = z * pb;
+        const int su = clampi(z + 1, a.nz) * pb, sd = clampi(z - 1, a.nz) * pb;
+        const Rsrc rb0 = make_rsrc(a.r, cb), rb1 = make_rsrc(a.r + N, cb), rb2 = make_rsrc(a.r + 2 * N, cb);
+        const Rsrc fb = make_rsrc(a.f, cb), mb = make_rsrc(a.m, cb);
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            d.r0[q] = r0p[zoff + pofs[q]];
-            d.r1[q] = r1p[zoff + pofs[q]];
-            d.r2[q] = r2p[zoff + pofs[q]];
+            const int vo = pofs[q] * 4;
+            d.r0[q] = ld(rb0, vo, so);
+            d.r1[q] = ld(rb1, vo, so);
+            d.r2[q] = ld(rb2, vo, so);
             if (FORCE) {
-                d.m[q] = a.m[zoff + pofs[q]];
-                d.fu[q] = a.f[zu + pofs[q]];
-                d.fd[q] = a.f[zd + pofs[q]];
+                d.m[q] = ld(mb, vo, so);
+                d.fu[q] = ld(fb, vo, su);
+                d.fd[q] = ld(fb, vo, sd);
             }
             if (DBL) {
-                d.mu[q] = a.m[zu + pofs[q]];
-                d.md[q] = a.m[zd + pofs[q]];
+                d.mu[q] = ld(mb, vo, su);
+                d.md[q] = ld(mb, vo, sd);
             }
         }
     };
@@ -282,15 +289,16 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
 #pragma unroll
             for (int j = 0; j < SRUN + 2 * R; ++j) v[j] = sx[(c * H + run * SRUN + j) * QTX + col];
             const int ox = x0 + col;
-            float* qc = a.q + c * N;
-            const int zoff = (z0 + py) * plane;
+            // c is uniform per wave (QTX * QTY / SRUN = 256 items per component)
+            const Rsrc qc = make_rsrc(a.q + __builtin_amdgcn_readfirstlane(c) * N, cb);
+            const int so = (z0 + py) * pb;
 #pragma unroll
             for (int rr = 0; rr < SRUN; ++rr) {
                 float sacc = 0.0f;
 #pragma unroll
                 for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[rr + j], sacc);
                 const int oy = y0 + run * SRUN + rr;
-                if (ox < a.nx && oy < a.ny) qc[zoff + oy * a.nx + ox] = sacc;
+                if (ox < a.nx && oy < a.ny) st(qc, (oy * a.nx + ox) * 4, so, sacc);
             }
         }
         __syncthreads();
@@ -372,8 +380,6 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
 {
     constexpr int K = 2 * R + 1;
     if (a.stop && *a.stop) return;  // the level has met its stopping rule
-    // element offsets fit in 32 bits (the ABI bounds N below 2^31); the three
-    // field components get their own base pointers
     const int col0 = (bid % a.colblocks) * ZNT + (int)threadIdx.x;
     if (!NORM && col0 >= (int)a.ncols) return;
     const bool act = col0 < (int)a.ncols;
@@ -381,22 +387,22 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
     const int xcol = col % a.nx, ycol = col / a.nx;
     const int z0 = (bid / a.colblocks) * a.zchunk;
     const int z1 = min(a.nz, z0 + a.zchunk);
-    const int plane = a.nx * a.ny;
-    const long N = (long)plane * a.nz;
-    const float* q0 = a.q;
-    const float* q1 = a.q + N;
-    const float* q2 = a.q + 2 * N;
-    float* o0 = a.out;
-    float* o1 = a.out + N;
-    float* o2 = a.out + 2 * N;
+    // buffer access: the lane's column is the per-lane byte offset, the plane
+    // a scalar offset; each field component has its own resource
+    const int pb = a.nx * a.ny * 4;
+    const long N = (long)a.nx * a.ny * a.nz;
+    const long cb = N * 4;
+    const Rsrc q0 = make_rsrc(a.q, cb), q1 = make_rsrc(a.q + N, cb), q2 = make_rsrc(a.q + 2 * N, cb);
+    const Rsrc o0 = make_rsrc(a.out, cb), o1 = make_rsrc(a.out + N, cb), o2 = make_rsrc(a.out + 2 * N, cb);
+    const int vo = col * 4;
     float ring[3][K];
     float n1[3], n2[3];  // the next two planes, loads in flight
     double s_dr = 0.0, s_r = 0.0;
     auto load = [&](int p, float* dst) {
-        const int o = clampi(z0 - R + p, a.nz) * plane + col;
-        dst[0] = q0[o];
-        dst[1] = q1[o];
-        dst[2] = q2[o];
+        const int so = clampi(z0 - R + p, a.nz) * pb;
+        dst[0] = ld(q0, vo, so);
+        dst[1] = ld(q1, vo, so);
+        dst[2] = ld(q2, vo, so);
     };
     const int nplanes = (z1 - z0) + 2 * R;
     load(0, n1);
@@ -415,7 +421,7 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
             load(p + 2, n2);  // past the chunk end this re-reads a clamped plane
             if (p >= K - 1) {
                 const int oz = z0 + p - 2 * R;
-                const int o = oz * plane + col;
+                const int so = oz * pb;
                 float nv[3], ov[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -425,15 +431,18 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
                     nv[c] = sacc;
                 }
                 if (NORM) {
-                    ov[0] = o0[o];
-                    ov[1] = o1[o];
-                    ov[2] = o2[o];
+                    ov[0] = ld(o0, vo, so);
+                    ov[1] = ld(o1, vo, so);
+                    ov[2] = ld(o2, vo, so);
                 }
                 if (act) {
-                    o0[o] = nv[0];
-                    o1[o] = nv[1];
-                    o2[o] = nv[2];
-                    if (WARP) a.m[o] = warp_at(a.ct, xcol, ycol, oz, nv[0], nv[1], nv[2], a.nx, a.ny, a.nz);
+                    st(o0, vo, so, nv[0]);
+                    st(o1, vo, so, nv[1]);
+                    st(o2, vo, so, nv[2]);
+                    if (WARP) {
+                        const WarpSrc w = warp_src(a.ct, a.nx, a.ny, a.nz);
+                        st(make_rsrc(a.m, cb), vo, so, warp_at(w, xcol, ycol, oz, nv[0], nv[1], nv[2]));
+                    }
                 }
                 if (NORM && act) {
                     const float dx = nv[0] - ov[0], dy = nv[1] - ov[1], dz = nv[2] - ov[2];
@@ -488,16 +497,18 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z_direct(ZArgs a)
     const int col = (blockIdx.x % a.colblocks) * ZNT + (int)threadIdx.x;
     const int z = blockIdx.x / a.colblocks;
     if (col >= (int)a.ncols) return;
-    // element offsets fit in 32 bits (the ABI bounds N below 2^31)
-    const int plane = a.nx * a.ny;
-    const long N = (long)plane * a.nz;
+    const int pb = a.nx * a.ny * 4;
+    const long N = (long)a.nx * a.ny * a.nz;
+    const long cb = N * 4;
+    const Rsrc q0 = make_rsrc(a.q, cb), q1 = make_rsrc(a.q + N, cb), q2 = make_rsrc(a.q + 2 * N, cb);
+    const int vo = col * 4;
     float v[3][K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const int o = clampi(z - R + j, a.nz) * plane + col;
-        v[0][j] = a.q[o];
-        v[1][j] = a.q[N + o];
-        v[2][j] = a.q[2 * N + o];
+        const int so = clampi(z - R + j, a.nz) * pb;
+        v[0][j] = ld(q0, vo, so);
+        v[1][j] = ld(q1, vo, so);
+        v[2][j] = ld(q2, vo, so);
     }
     float nv[3];
 #pragma unroll
@@ -507,11 +518,14 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z_direct(ZArgs a)
         for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[c][j], sacc);
         nv[c] = sacc;
     }
-    const int o = z * plane + col;
-    a.out[o] = nv[0];
-    a.out[N + o] = nv[1];
-    a.out[2 * N + o] = nv[2];
-    if (WARP) a.m[o] = warp_at(a.ct, col % a.nx, col / a.nx, z, nv[0], nv[1], nv[2], a.nx, a.ny, a.nz);
+    const int so = z * pb;
+    st(make_rsrc(a.out, cb), vo, so, nv[0]);
+    st(make_rsrc(a.out + N, cb), vo, so, nv[1]);
+    st(make_rsrc(a.out + 2 * N, cb), vo, so, nv[2]);
+    if (WARP) {
+        const WarpSrc w = warp_src(a.ct, a.nx, a.ny, a.nz);
+        st(make_rsrc(a.m, cb), vo, so, warp_at(w, col % a.nx, col / a.nx, z, nv[0], nv[1], nv[2]));
+    }
 }
 
 // Sec. 2.3 stopping rule after iteration k of a level: l^(k) = sum |dr| /
