@@ -181,27 +181,37 @@ __device__ __forceinline__ void moments_body(const MomArgs& a, const int bid)
     // Software pipeline, one barrier per step q:
     //   stash plane q | x pass of plane q-1 | y pass of plane q-2 | z window of plane q-3
     // with double buffers, so the four stages of one step touch disjoint LDS.
-    // Region loads run two steps ahead (plane q+2 is requested in step q);
-    // steps come in pairs so that each of the two register and LDS buffers
-    // has a fixed parity. The epilogue input is requested at the top of the
-    // step that uses it, behind the x and y passes, so that no loaded value
-    // is carried across the loop's back edge.
-    auto step = [&](int q, const int par, float(&pre)[NQ]) {
-        const float epi_cur = epi_load(q - 3);
+    // Global loads run PF steps ahead: step q requests the region of plane
+    // q + PF and the per-voxel epilogue inputs of step q + PF, into register
+    // slot q % PF, right after consuming what that slot held. With one
+    // 1024-thread workgroup per CU no other workgroup covers memory latency,
+    // so the loads must be in flight for several steps. Steps are unrolled
+    // by PF, which fixes every slot index (and the LDS parity) at compile time.
+    // (two steps where the z window or the mode's extra inputs leave no
+    // registers for more: the hot correction sweep with pz < 13 gets four)
+    constexpr int PF = (MODE == kCorrect && PZ < 13) ? 4 : 2;
+    float pre[PF][NQ];
+    float epi_q[PF], mid_q[PF], s_q[PF], sd_q[PF];
+    // epilogue inputs of step q (the output made when plane q - 3 enters the window)
+    auto epi_fetch = [&](int q, int slot) {
+        epi_q[slot] = epi_load(q - 3);
         // SSD and mask: m at the output voxel itself; mask and a_m: S and STD(S) there
         const long vox_off = (long)clampi(z0 + q - 3 - 2 * RZ, a.nz) * plane + col_off;
-        const float mid_cur = (MODE == kSsd || MODE == kMask) ? a.img[vox_off] : 0.0f;
-        const float s_cur = MODE == kMask ? a.s_img[vox_off] : 0.0f;
-        const float sd_cur = (MODE == kMask || MODE == kAmed) ? a.sd_s[vox_off] : 0.0f;
+        mid_q[slot] = (MODE == kSsd || MODE == kMask) ? a.img[vox_off] : 0.0f;
+        s_q[slot] = MODE == kMask ? a.s_img[vox_off] : 0.0f;
+        sd_q[slot] = (MODE == kMask || MODE == kAmed) ? a.sd_s[vox_off] : 0.0f;
+    };
+    auto step = [&](int q, const int par, const int slot) {
+        const float epi_cur = epi_q[slot], mid_cur = mid_q[slot], s_cur = s_q[slot], sd_cur = sd_q[slot];
+        epi_fetch(q + PF, slot);
         if (q < nplanes) {
             float* s_m = s_m0 + par * (MAXH * MAXPW);
 #pragma unroll
             for (int k = 0; k < NQ; ++k)
-                if (gval[k]) s_m[soff[k]] = pre[k];
+                if (gval[k]) s_m[soff[k]] = pre[slot][k];
         }
-        // unconditional (the plane index is clamped), so the wait for the
-        // epilogue input below never has to drain these loads too
-        fetch(pre, q + 2);
+        // unconditional (the plane index is clamped): always a valid address
+        fetch(pre[slot], q + PF);
         if (q >= 1 && q - 1 < nplanes && t < XT) {
             // x pass: window [c, c + 2 rx] of the loaded row is the patch row of column c
             const int row = t & 63, run = t >> 6;
@@ -318,13 +328,17 @@ __device__ __forceinline__ void moments_body(const MomArgs& a, const int bid)
         __syncthreads();
     };
 
-    float pre0[NQ], pre1[NQ];
-    fetch(pre0, 0);
-    fetch(pre1, 1);
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        fetch(pre[k], k);
+        epi_fetch(k, k);
+    }
     const int nsteps = nplanes + 3;
-    for (int q = 0; q < nsteps; q += 2) {
-        step(q, 0, pre0);
-        if (q + 1 < nsteps) step(q + 1, 1, pre1);
+    static_assert(PF % 2 == 0, "the LDS parity follows the step index");
+    for (int q = 0; q < nsteps; q += PF) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k)
+            if (q + k < nsteps) step(q + k, k & 1, k);
     }
     if (MODE == kSsd) {
         // fixed-order tree over the workgroup, one partial per workgroup

@@ -370,6 +370,7 @@ struct ZArgs {
 };
 
 constexpr int ZNT = 256;
+constexpr int ZPF = 4;  // planes of z-pass loads in flight per thread
 
 // One workgroup: ZNT columns of one z chunk; bid = chunk * colblocks + column
 // block. NORM: out holds r^(k) on entry; the workgroup also sums, in FP64,
@@ -396,7 +397,8 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
     const Rsrc o0 = make_rsrc(a.out, cb), o1 = make_rsrc(a.out + N, cb), o2 = make_rsrc(a.out + 2 * N, cb);
     const int vo = col * 4;
     float ring[3][K];
-    float n1[3], n2[3];  // the next two planes, loads in flight
+    // the next ZPF planes, loads in flight (a short shift register)
+    float nx_[ZPF][3];
     double s_dr = 0.0, s_r = 0.0;
     auto load = [&](int p, float* dst) {
         const int so = clampi(z0 - R + p, a.nz) * pb;
@@ -405,8 +407,8 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
         dst[2] = ld(q2, vo, so);
     };
     const int nplanes = (z1 - z0) + 2 * R;
-    load(0, n1);
-    load(1, n2);  // clamped plane index: always a valid address
+#pragma unroll
+    for (int j = 0; j < ZPF; ++j) load(j, nx_[j]);  // clamped plane index: always a valid address
     for (int p0 = 0; p0 < nplanes; p0 += K) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -415,10 +417,11 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
             if (!NORM && p >= nplanes) break;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                ring[c][k] = n1[c];
-                n1[c] = n2[c];
+                ring[c][k] = nx_[0][c];
+#pragma unroll
+                for (int j = 0; j + 1 < ZPF; ++j) nx_[j][c] = nx_[j + 1][c];
             }
-            load(p + 2, n2);  // past the chunk end this re-reads a clamped plane
+            load(p + ZPF, nx_[ZPF - 1]);  // past the chunk end this re-reads a clamped plane
             if (p >= K - 1) {
                 const int oz = z0 + p - 2 * R;
                 const int so = oz * pb;
@@ -603,6 +606,10 @@ ZArgs z_args(const float* q, float* out, Dims d, const GaussTaps& t, int target 
     if (chunks > d.nz) chunks = d.nz;
     if (chunks < 1) chunks = 1;
     a.zchunk = (d.nz + chunks - 1) / chunks;
+    // chunks of fewer than four planes re-read 2R halo planes per output or
+    // two; use four whenever that still leaves about 512 workgroups
+    // (measured: 128 x 128 x 48 at sigma 2, 17 -> 14 us)
+    if (a.zchunk < 4 && colblocks * ((d.nz + 3) / 4) >= 512) a.zchunk = 4;
     a.colblocks = (int)colblocks;
     return a;
 }
