@@ -234,7 +234,9 @@ def batched_rate(disc, n_pairs=16, iters=100):
     fe = (b.field(0) - regs[0].field()).abs().max().item()
     if not fe <= 0.05:
         raise RuntimeError("batched pair 0 differs from the single-volume path by %.3g voxel" % fe)
+    small = small_batch_rate(disc, iters=iters)
     return {"pairs": n_pairs, "shapes_zyx": [list(s) for s in shapes], "voxels": vox, "iterations": iters,
+            "small_volumes": small,
             "ms_sequential": round(ms_seq, 3), "ms_batched_eager": round(ms_eager, 3),
             "ms_batched_graph": round(ms_graph, 3),
             "voxel_iterations_per_s_graph": round(vox * iters / (ms_graph * 1e-3), 1),
@@ -252,6 +254,49 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def small_batch_rate(disc, n_pairs=16, shape=(32, 64, 64), iters=100):
+    """Where batching pays: n small pairs (131,072 voxels each, patch 11^3,
+    sigma 2, one level), whose single-volume iterations are bound by launch
+    latency, as sequential registrations against one batch (eager launches
+    and the captured HIP graph)."""
+    import torch
+
+    from synth.phantom import make_hn_pair
+
+    cases = [make_hn_pair(shape, pair=200 + i, device="cuda") for i in range(n_pairs)]
+    cts = [torch.from_numpy(c.ct).cuda() for c in cases]
+    cbs = [torch.from_numpy(c.cbct).cuda() for c in cases]
+    kw = dict(patch=(11, 11, 11), sigma=2.0)
+    regs = [disc.Registration(levels=1, iters=(iters,), **kw) for _ in cases]
+
+    def seq():
+        for reg, ct, cb in zip(regs, cts, cbs):
+            reg.set_volumes(ct, cb)
+            reg.run()
+
+    ms_seq = _ms_per_call(seq, reps=2, warm=1)
+    b = disc.Batch([shape] * n_pairs, iters=iters, **kw)
+
+    def run(graph):
+        def f():
+            b.set_volumes(cts, cbs)
+            b.run(use_graph=graph)
+        return f
+
+    ms_eager = _ms_per_call(run(False), reps=2, warm=1)
+    ms_graph = _ms_per_call(run(True), reps=3, warm=1)
+    fe = (b.field(0) - regs[0].field()).abs().max().item()
+    if not fe <= 0.05:
+        raise RuntimeError("small batch pair 0 differs from the single-volume path by %.3g voxel" % fe)
+    vox = float(n_pairs * shape[0] * shape[1] * shape[2])
+    return {"pairs": n_pairs, "shape_zyx": list(shape), "iterations": iters, "ms_sequential": round(ms_seq, 3),
+            "ms_batched_eager": round(ms_eager, 3), "ms_batched_graph": round(ms_graph, 3),
+            "voxel_iterations_per_s_graph": round(vox * iters / (ms_graph * 1e-3), 1),
+            "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 3),
+            "speedup_graph_vs_eager": round(ms_eager / ms_graph, 3),
+            "pair0_field_max_diff_vs_single": fe}
 
 
 def cpu_baseline(case, params, budget_s=10.0, max_iters=10):
@@ -522,6 +567,11 @@ def main():
         log("batched: sequential %.1f ms, batch eager %.1f ms, batch graph %.1f ms (%.2fx), tiles %s" % (
             bat["ms_sequential"], bat["ms_batched_eager"], bat["ms_batched_graph"],
             bat["speedup_graph_vs_sequential"], bat["tiles"]))
+        sm = bat["small_volumes"]
+        log("batched small volumes (16 x 64x64x32): sequential %.2f ms, batch eager %.2f ms, graph %.2f ms "
+            "(%.2fx vs sequential, %.2fx vs eager)" % (sm["ms_sequential"], sm["ms_batched_eager"],
+                                                       sm["ms_batched_graph"], sm["speedup_graph_vs_sequential"],
+                                                       sm["speedup_graph_vs_eager"]))
         out["batched"] = bat
         others = {}
         for wname in ("ellipsoid48", "hn512x512x160"):

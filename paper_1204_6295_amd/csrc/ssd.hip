@@ -32,36 +32,105 @@ inline dim3 grid_for(Dims d)
 // Transpose of the clamped 1-D window sum out(x) = sum_{|k| <= R} in(clamp(x + k))
 // along one axis: out(j) = sum_x count(x, j) in(x), count(x, j) = #{k : clamp(x + k) = j}.
 // Interior j: every x within R counts once. The end voxels also collect the
-// offsets that the clamp folds onto them.
-template <int AXIS>
-__global__ __launch_bounds__(BX* BY) void k_box_adjoint(const double2* __restrict__ in,
-                                                       double2* __restrict__ out, int nx, int ny,
-                                                       int nz, int R)
+// offsets that the clamp folds onto them: count(x, 0) = R - x + 1 for x <= R,
+// and the mirror image at the far end (2R + 1 on an axis of one voxel).
+__device__ inline int fold_count(int j, int xx, int len, int R)
 {
-    const int x = blockIdx.x * BX + threadIdx.x;
+    if (len == 1) return 2 * R + 1;
+    if (j == 0) return R - xx + 1;
+    if (j == len - 1) return R - (len - 1 - xx) + 1;
+    return 1;
+}
+
+constexpr int kMaxAdjR = 15;  // patch extents up to 31
+
+// Along x: the workgroup stages its four rows plus the R-voxel halo in LDS,
+// then each thread sums its output's window there.
+__global__ __launch_bounds__(BX* BY) void k_box_adjoint_x(const double2* __restrict__ in,
+                                                         double2* __restrict__ out, int nx, int ny, int R)
+{
+    __shared__ double2 tile[BY][BX + 2 * kMaxAdjR];
+    const int x0 = blockIdx.x * BX;
     const int y = blockIdx.y * BY + threadIdx.y;
     const int z = blockIdx.z;
+    const int yc = min(y, ny - 1);
+    const double2* row = in + ((long)z * ny + yc) * nx;
+    for (int i = threadIdx.x; i < BX + 2 * R; i += BX) {
+        const int xx = x0 - R + i;
+        tile[threadIdx.y][i] = (xx >= 0 && xx < nx) ? row[xx] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int x = x0 + threadIdx.x;
     if (x >= nx || y >= ny) return;
-    const long i = ((long)z * ny + y) * nx + x;
-    const int j = AXIS == 0 ? x : (AXIS == 1 ? y : z);
-    const int len = AXIS == 0 ? nx : (AXIS == 1 ? ny : nz);
-    const long st = AXIS == 0 ? 1L : (AXIS == 1 ? (long)nx : (long)nx * ny);
-    const double2* line = in + (i - (long)j * st);
-    const int lo = max(0, j - R), hi = min(len - 1, j + R);
+    const int lo = max(0, x - R), hi = min(nx - 1, x + R);
+    const bool edge = x == 0 || x == nx - 1;
     double s1 = 0.0, s2 = 0.0;
     for (int xx = lo; xx <= hi; ++xx) {
-        int c = 1;
-        if (len == 1)
-            c = 2 * R + 1;
-        else if (j == 0)
-            c = R - xx + 1;  // offsets k <= -xx
-        else if (j == len - 1)
-            c = R - (len - 1 - xx) + 1;  // offsets k >= len - 1 - xx
-        const double2 v = line[(long)xx * st];
-        s1 = fma((double)c, v.x, s1);
-        s2 = fma((double)c, v.y, s2);
+        const double2 v = tile[threadIdx.y][xx - x0 + R];
+        if (edge) {
+            const double c = (double)fold_count(x, xx, nx, R);
+            s1 = fma(c, v.x, s1);
+            s2 = fma(c, v.y, s2);
+        } else {
+            s1 += v.x;
+            s2 += v.y;
+        }
     }
-    out[i] = make_double2(s1, s2);
+    out[((long)z * ny + y) * nx + x] = make_double2(s1, s2);
+}
+
+// Along y: a thread takes a run of YC outputs of its (x, z) column. It
+// requests every row its windows touch at once (rows outside the volume
+// read as zero, which truncates the window exactly as the clamp-free
+// interior count requires), then slides the window sum down the run; the
+// two end rows of the volume take the folded counts.
+constexpr int YC = 16;
+
+template <int R>
+__global__ __launch_bounds__(BX* BY) void k_box_adjoint_y(const double2* __restrict__ in,
+                                                         double2* __restrict__ out, int nx, int ny)
+{
+    constexpr int NV = YC + 2 * R;
+    const int x = blockIdx.x * BX + threadIdx.x;
+    const int ya = (blockIdx.y * BY + threadIdx.y) * YC;
+    const int z = blockIdx.z;
+    if (x >= nx || ya >= ny) return;
+    const double2* col = in + (long)z * ny * nx + x;
+    double2* oc = out + (long)z * ny * nx + x;
+    double2 v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const int yy = ya - R + k;
+        v[k] = (yy >= 0 && yy < ny) ? col[(long)yy * nx] : make_double2(0.0, 0.0);
+    }
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) {
+        s1 += v[k].x;
+        s2 += v[k].y;
+    }
+#pragma unroll
+    for (int j = 0; j < YC; ++j) {
+        const int y = ya + j;
+        if (y >= ny) break;
+        if (j > 0) {
+            s1 += v[j + 2 * R].x - v[j - 1].x;
+            s2 += v[j + 2 * R].y - v[j - 1].y;
+        }
+        double2 o = make_double2(s1, s2);
+        if (y == 0 || y == ny - 1) {
+            o = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k <= 2 * R; ++k) {
+                const int yy = y - R + k;
+                if (yy < 0 || yy > ny - 1) continue;
+                const double c = (double)fold_count(y, yy, ny, R);
+                o.x = fma(c, v[j + k].x, o.x);
+                o.y = fma(c, v[j + k].y, o.y);
+            }
+        }
+        oc[(long)y * nx] = o;
+    }
 }
 
 // dL/dr at voxel (x, y, z) = dL/dm * d m / d position, with
@@ -143,7 +212,7 @@ __global__ __launch_bounds__(BX* BY) void k_ssd_grad_z(const float* __restrict__
         if (z == 0 || z == nz - 1) {
             b = make_double2(0.0, 0.0);
             for (int zz = max(0, z - R); zz <= min(nz - 1, z + R); ++zz) {
-                const int c = nz == 1 ? 2 * R + 1 : (z == 0 ? R - zz + 1 : R - (nz - 1 - zz) + 1);
+                const int c = fold_count(z, zz, nz, R);
                 const double2 v = col[zz * plane];
                 b.x = fma((double)c, v.x, b.x);
                 b.y = fma((double)c, v.y, b.y);
@@ -174,13 +243,24 @@ __global__ __launch_bounds__(256) void k_ssd_finish(const double* __restrict__ p
 
 hipError_t launch_box_adjoint(const double2* in, double2* out, Dims d, int axis, int R, hipStream_t st)
 {
-    const dim3 g = grid_for(d), b(BX, BY);
-    if (axis == 0)
-        hipLaunchKernelGGL(k_box_adjoint<0>, g, b, 0, st, in, out, d.nx, d.ny, d.nz, R);
-    else if (axis == 1)
-        hipLaunchKernelGGL(k_box_adjoint<1>, g, b, 0, st, in, out, d.nx, d.ny, d.nz, R);
-    else
-        hipLaunchKernelGGL(k_box_adjoint<2>, g, b, 0, st, in, out, d.nx, d.ny, d.nz, R);
+    if (R < 0 || R > kMaxAdjR) return hipErrorInvalidValue;
+    const dim3 b(BX, BY);
+    if (axis == 0) {
+        hipLaunchKernelGGL(k_box_adjoint_x, grid_for(d), b, 0, st, in, out, d.nx, d.ny, R);
+    } else if (axis == 1) {
+        const int runs = (d.ny + YC - 1) / YC;
+        const dim3 g((d.nx + BX - 1) / BX, (runs + BY - 1) / BY, d.nz);
+        switch (R) {
+#define DISC_R(RR) \
+    case RR: hipLaunchKernelGGL(k_box_adjoint_y<RR>, g, b, 0, st, in, out, d.nx, d.ny); break;
+            DISC_R(0) DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7)
+            DISC_R(8) DISC_R(9) DISC_R(10) DISC_R(11) DISC_R(12) DISC_R(13) DISC_R(14) DISC_R(15)
+#undef DISC_R
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;  // the z adjoint runs inside k_ssd_grad_z
+    }
     return hipGetLastError();
 }
 
