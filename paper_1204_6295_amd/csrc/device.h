@@ -76,7 +76,7 @@ __device__ inline void st(Rsrc r, int voff, int soff, float v)
 // held in scalar registers.
 struct WarpSrc {
     Rsrc ct;
-    int nx, ny;
+    int nx, ny, nz;
     int xm, ym, zm;  // largest lowest-corner index per axis: max(n - 2, 0)
     int so[8];
 };
@@ -87,6 +87,7 @@ __device__ inline WarpSrc warp_src(const float* ct, int nx, int ny, int nz)
     w.ct = make_rsrc(ct, (long)nx * ny * nz * 4);
     w.nx = nx;
     w.ny = ny;
+    w.nz = nz;
     w.xm = nx > 1 ? nx - 2 : 0;
     w.ym = ny > 1 ? ny - 2 : 0;
     w.zm = nz > 1 ? nz - 2 : 0;

@@ -135,90 +135,106 @@ __global__ __launch_bounds__(BX* BY) void k_box_adjoint_y(const double2* __restr
 
 // dL/dr at voxel (x, y, z) = dL/dm * d m / d position, with
 // dL/dm = 2 D - 2 (m B(beta) + B(gamma)) and the derivative of the trilinear
-// interpolant of the warp (same floor and clamp conventions: the cell is the
-// one the warp samples). b = (B(beta), B(gamma)) at the voxel.
-__device__ __forceinline__ void grad_at(const float* __restrict__ ct, const float* __restrict__ r,
-                                        const float* __restrict__ m, const float* __restrict__ dres,
-                                        const float* __restrict__ scale, float* __restrict__ grad, int x,
-                                        int y, int z, int nx, int ny, int nz, double2 b)
+// interpolant of the warp in the cell the warp samples (the same clamped
+// cell as warp_at: lowest corner clamped to [0, n - 2], weight to [0, 1]).
+// Along an axis where the sample lies outside [0, n - 1] both corners of the
+// clamped interpolant are the same voxel, so that component is 0. b =
+// (B(beta), B(gamma)) at the voxel; vo / so: per-lane and scalar byte offsets
+// of the voxel.
+__device__ __forceinline__ void grad_at(const WarpSrc& w, Rsrc rb0, Rsrc rb1, Rsrc rb2, Rsrc mb, Rsrc db, Rsrc gb0,
+                                        Rsrc gb1, Rsrc gb2, double sc, int x, int y, int z, int vo, int so,
+                                        double2 b)
 {
-    const long N = (long)nx * ny * nz;
-    const long i = ((long)z * ny + y) * nx + x;
-    const float rx = r[i], ry = r[N + i], rz = r[2 * N + i];
-    const float tx = rx - floorf(rx), ty = ry - floorf(ry), tz = rz - floorf(rz);
+    const float rx = ld(rb0, vo, so), ry = ld(rb1, vo, so), rz = ld(rb2, vo, so);
+    const float fx = floorf(rx), fy = floorf(ry), fz = floorf(rz);
     const int ix = x + floor_to_int(rx), iy = y + floor_to_int(ry), iz = z + floor_to_int(rz);
-    const int x0 = clampi(ix, nx), x1 = clampi(ix + 1, nx);
-    const int y0 = clampi(iy, ny), y1 = clampi(iy + 1, ny);
-    const int z0 = clampi(iz, nz), z1 = clampi(iz + 1, nz);
-    const float* p00 = ct + ((long)z0 * ny + y0) * nx;
-    const float* p01 = ct + ((long)z0 * ny + y1) * nx;
-    const float* p10 = ct + ((long)z1 * ny + y0) * nx;
-    const float* p11 = ct + ((long)z1 * ny + y1) * nx;
-    // corner values c[z][y][x]
-    const float c000 = p00[x0], c001 = p00[x1], c010 = p01[x0], c011 = p01[x1];
-    const float c100 = p10[x0], c101 = p10[x1], c110 = p11[x0], c111 = p11[x1];
+    const int xa = min(max(ix, 0), w.xm), ya = min(max(iy, 0), w.ym), za = min(max(iz, 0), w.zm);
+    const float tx = fminf(fmaxf((float)(ix - xa) + (rx - fx), 0.0f), 1.0f);
+    const float ty = fminf(fmaxf((float)(iy - ya) + (ry - fy), 0.0f), 1.0f);
+    const float tz = fminf(fmaxf((float)(iz - za) + (rz - fz), 0.0f), 1.0f);
+    const bool inx = ix >= 0 && ix <= w.nx - 2, iny = iy >= 0 && iy <= w.ny - 2, inz = iz >= 0 && iz <= w.nz - 2;
+    const int v = ((za * w.ny + ya) * w.nx + xa) * 4;
+    float c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = ld(w.ct, v, w.so[k]);
+    // corner k: bit 0 +x, bit 1 +y, bit 2 +z
     const float ux = 1.0f - tx, uy = 1.0f - ty, uz = 1.0f - tz;
-    const float gx = uz * (uy * (c001 - c000) + ty * (c011 - c010)) + tz * (uy * (c101 - c100) + ty * (c111 - c110));
-    const float gy = uz * (ux * (c010 - c000) + tx * (c011 - c001)) + tz * (ux * (c110 - c100) + tx * (c111 - c101));
-    const float gz = uy * (ux * (c100 - c000) + tx * (c101 - c001)) + ty * (ux * (c110 - c010) + tx * (c111 - c011));
-    const double G = 2.0 * ((double)dres[i] - fma((double)m[i], b.x, b.y));
-    const double s = scale ? (double)scale[0] : 1.0;
-    const double sg = s * G;
-    grad[i] = (float)(sg * (double)gx);
-    grad[N + i] = (float)(sg * (double)gy);
-    grad[2 * N + i] = (float)(sg * (double)gz);
+    const float gx = inx ? uz * (uy * (c[1] - c[0]) + ty * (c[3] - c[2])) + tz * (uy * (c[5] - c[4]) + ty * (c[7] - c[6]))
+                         : 0.0f;
+    const float gy = iny ? uz * (ux * (c[2] - c[0]) + tx * (c[3] - c[1])) + tz * (ux * (c[6] - c[4]) + tx * (c[7] - c[5]))
+                         : 0.0f;
+    const float gz = inz ? uy * (ux * (c[4] - c[0]) + tx * (c[5] - c[1])) + ty * (ux * (c[6] - c[2]) + tx * (c[7] - c[3]))
+                         : 0.0f;
+    const double G = 2.0 * ((double)ld(db, vo, so) - fma((double)ld(mb, vo, so), b.x, b.y));
+    const double sg = sc * G;
+    st(gb0, vo, so, (float)(sg * (double)gx));
+    st(gb1, vo, so, (float)(sg * (double)gy));
+    st(gb2, vo, so, (float)(sg * (double)gz));
 }
 
-// The z adjoint fused with the gradient: a thread walks its column through
-// a chunk of zchunk planes, keeping the in-range z window sum of the x-y
-// adjoint t (see k_box_adjoint) as a running sum; the end planes take the
-// clamp's folded offsets by a direct sum. The gradient then follows at each
-// voxel without B(beta), B(gamma) going through memory.
+// The z adjoint fused with the gradient: a thread takes a run of ZC planes of
+// its column, requests every plane of the x-y adjoint t their windows touch
+// at once (planes outside the volume read as zero), slides the z window sum
+// down the run (the end planes take the clamp's folded counts), and forms the
+// gradient at each voxel; B(beta), B(gamma) never go through memory.
+constexpr int ZC = 16;
+
+template <int R>
 __global__ __launch_bounds__(BX* BY) void k_ssd_grad_z(const float* __restrict__ ct,
                                                       const float* __restrict__ r,
                                                       const float* __restrict__ m,
                                                       const float* __restrict__ dres,
                                                       const double2* __restrict__ t,
                                                       const float* __restrict__ scale,
-                                                      float* __restrict__ grad, int nx, int ny,
-                                                      int nz, int R, int zchunk)
+                                                      float* __restrict__ grad, int nx, int ny, int nz)
 {
+    constexpr int NV = ZC + 2 * R;
     const int x = blockIdx.x * BX + threadIdx.x;
     const int y = blockIdx.y * BY + threadIdx.y;
-    const int za = blockIdx.z * zchunk, zb = min(nz, za + zchunk);
+    const int za = blockIdx.z * ZC;
     if (x >= nx || y >= ny) return;
     const long plane = (long)nx * ny;
+    const long N = plane * nz, cb = N * 4;
     const double2* col = t + (long)y * nx + x;
-    double s1 = 0.0, s2 = 0.0;
-    for (int zz = max(0, za - R); zz <= min(nz - 1, za + R); ++zz) {
-        const double2 v = col[zz * plane];
-        s1 += v.x;
-        s2 += v.y;
+    double2 v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const int zz = za - R + k;
+        v[k] = (zz >= 0 && zz < nz) ? col[zz * plane] : make_double2(0.0, 0.0);
     }
-    for (int z = za; z < zb; ++z) {
-        if (z > za) {
-            if (z + R <= nz - 1) {
-                const double2 v = col[(z + R) * plane];
-                s1 += v.x;
-                s2 += v.y;
-            }
-            if (z - 1 - R >= 0) {
-                const double2 v = col[(z - 1 - R) * plane];
-                s1 -= v.x;
-                s2 -= v.y;
-            }
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) {
+        s1 += v[k].x;
+        s2 += v[k].y;
+    }
+    const WarpSrc w = warp_src(ct, nx, ny, nz);
+    const Rsrc rb0 = make_rsrc(r, cb), rb1 = make_rsrc(r + N, cb), rb2 = make_rsrc(r + 2 * N, cb);
+    const Rsrc gb0 = make_rsrc(grad, cb), gb1 = make_rsrc(grad + N, cb), gb2 = make_rsrc(grad + 2 * N, cb);
+    const Rsrc mb = make_rsrc(m, cb), db = make_rsrc(dres, cb);
+    const double sc = scale ? (double)scale[0] : 1.0;
+    const int vo = (y * nx + x) * 4, pb = (int)plane * 4;
+#pragma unroll
+    for (int j = 0; j < ZC; ++j) {
+        const int z = za + j;
+        if (z >= nz) break;
+        if (j > 0) {
+            s1 += v[j + 2 * R].x - v[j - 1].x;
+            s2 += v[j + 2 * R].y - v[j - 1].y;
         }
-        double2 b = make_double2(s1, s2);
+        double2 bz = make_double2(s1, s2);
         if (z == 0 || z == nz - 1) {
-            b = make_double2(0.0, 0.0);
-            for (int zz = max(0, z - R); zz <= min(nz - 1, z + R); ++zz) {
-                const int c = fold_count(z, zz, nz, R);
-                const double2 v = col[zz * plane];
-                b.x = fma((double)c, v.x, b.x);
-                b.y = fma((double)c, v.y, b.y);
+            bz = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k <= 2 * R; ++k) {
+                const int zz = z - R + k;
+                if (zz < 0 || zz > nz - 1) continue;
+                const double c = (double)fold_count(z, zz, nz, R);
+                bz.x = fma(c, v[j + k].x, bz.x);
+                bz.y = fma(c, v[j + k].y, bz.y);
             }
         }
-        grad_at(ct, r, m, dres, scale, grad, x, y, z, nx, ny, nz, b);
+        grad_at(w, rb0, rb1, rb2, mb, db, gb0, gb1, gb2, sc, x, y, z, vo, z * pb, bz);
     }
 }
 
@@ -267,12 +283,17 @@ hipError_t launch_box_adjoint(const double2* in, double2* out, Dims d, int axis,
 hipError_t launch_ssd_grad_z(const float* ct, const float* r, const float* m, const float* dres,
                              const double2* t, const float* scale, float* grad, Dims d, int R, hipStream_t st)
 {
-    // about 8 planes per chunk: enough workgroups, short window warm-ups
-    const int chunks = std::max(1, (d.nz + 7) / 8);
-    const int zchunk = (d.nz + chunks - 1) / chunks;
-    const dim3 g((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + zchunk - 1) / zchunk);
-    hipLaunchKernelGGL(k_ssd_grad_z, g, dim3(BX, BY), 0, st, ct, r, m, dres, t, scale, grad, d.nx, d.ny, d.nz,
-                       R, zchunk);
+    const dim3 g((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, (d.nz + ZC - 1) / ZC);
+    switch (R) {
+#define DISC_R(RR)                                                                                          \
+    case RR:                                                                                                \
+        hipLaunchKernelGGL(k_ssd_grad_z<RR>, g, dim3(BX, BY), 0, st, ct, r, m, dres, t, scale, grad, d.nx, d.ny, \
+                           d.nz);                                                                           \
+        break;
+        DISC_R(0) DISC_R(1) DISC_R(2) DISC_R(3) DISC_R(4) DISC_R(5) DISC_R(6) DISC_R(7)
+#undef DISC_R
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
