@@ -1,0 +1,265 @@
+// Patch moments (Eq. 3) and the moment-matching correction (Eq. 5-6) for
+// isotropic patches on large volumes, z first.
+//
+// A 512-thread workgroup owns a 32 x 32 column tile and a chunk of output
+// planes. Every column of the tile plus its in-plane patch halo keeps the
+// FP64 sums of m and m^2 over its z window in registers, advanced by one
+// plane per step (add the plane entering the window, subtract the one
+// leaving it; both loads are requested two steps ahead). Per output plane:
+//   store   the column sums in LDS;                         barrier
+//   x pass  sliding sums along x of those, 4 outputs per item, one lane per
+//           region row (row-fastest lanes: conflict-free 16-byte accesses);
+//                                                            barrier
+//   y pass  sliding sums along y, 2 outputs per item (one item per
+//           thread), then the epilogue I'_s = E(M) + STD(M) Y at those voxels.
+// The x and y passes run only on output planes (the z halo costs one add
+// per column and plane), and the workgroup's 51 KB of LDS lets two of them
+// share a CU, so one workgroup's barrier waits overlap the other's work.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace disc {
+
+namespace {
+
+constexpr int ZTS = 32;   // output tile edge
+constexpr int ZFT = 512;  // threads per workgroup
+constexpr int ZRUN = 4;   // outputs per x item
+constexpr int YRUN = 2;   // outputs per y item (every thread takes one)
+constexpr int ZPF = 2;    // steps of m loads in flight
+
+struct ZfArgs {
+    const float* m;    // deformed moving image
+    const float* ys;   // standardised static image (flat patches flagged in bit 0)
+    float* f;          // I'_s
+    const int* stop;   // level's stop flag (stopping rule), may be null
+    int nx, ny, nz;
+    int tiles_x, tiles_y, zchunk, nblocks;
+    double inv_n;
+};
+
+template <int R>
+struct ZfLds {
+    static constexpr int W = ZTS + 2 * R;  // region edge
+    static constexpr int ZP = W | 1;       // odd pitch (double2) of the z-sum rows
+    static constexpr int XP = W | 1;       // odd pitch of the column-major x sums
+    static constexpr size_t BYTES = ((size_t)W * ZP + (size_t)ZTS * XP) * sizeof(double2);
+};
+
+template <int PZ, int R>
+__global__ __launch_bounds__(ZFT) void k_correct_zf(ZfArgs a)
+{
+    constexpr int RZ = PZ / 2;
+    using L = ZfLds<R>;
+    constexpr int W = L::W, ZP = L::ZP, XP = L::XP;
+    constexpr int NC = (W * W + ZFT - 1) / ZFT;  // region columns per thread
+    constexpr int XI = W * (ZTS / ZRUN);          // x items
+    constexpr int YI = ZTS * (ZTS / YRUN);        // y items
+    static_assert(XI <= ZFT && YI <= ZFT, "one x and one y item per thread");
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2* zs = reinterpret_cast<double2*>(smem);
+    double2* xs = zs + W * ZP;
+    if (a.stop && *a.stop) return;  // the level has met its stopping rule
+
+    const int lb = xcd_logical_block(blockIdx.x, a.nblocks);
+    const int bx = lb % a.tiles_x;
+    const int rest = lb / a.tiles_x;
+    const int by = rest % a.tiles_y;
+    const int bz = rest / a.tiles_y;
+    const int x0 = bx * ZTS, y0 = by * ZTS;
+    const int z0 = bz * a.zchunk, z1 = min(a.nz, z0 + a.zchunk);
+    const int t = threadIdx.x;
+    const int pb = a.nx * a.ny * 4;
+    const long vb = (long)pb * a.nz;
+    const Rsrc mb = make_rsrc(a.m, vb);
+
+    // this thread's region columns: clamped source offset and LDS slot
+    int goff[NC], slot[NC];
+    bool cval[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        const int i = t + q * ZFT;
+        const int row = i / W, col = i - row * W;
+        cval[q] = i < W * W;
+        goff[q] = cval[q] ? (clampi(y0 - R + row, a.ny) * a.nx + clampi(x0 - R + col, a.nx)) * 4 : 0;
+        slot[q] = cval[q] ? row * ZP + col : 0;
+    }
+    // z window of output plane z: m(clamp(z + k)), |k| <= RZ
+    double s1[NC], s2[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) s1[q] = s2[q] = 0.0;
+#pragma unroll
+    for (int k = -RZ; k <= RZ; ++k) {
+        const int so = clampi(z0 + k, a.nz) * pb;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const double v = (double)ld(mb, goff[q], so);
+            s1[q] += v;
+            s2[q] = fma(v, v, s2[q]);
+        }
+    }
+    // loads of step j (output plane z0 + j, j >= 1): the plane entering the
+    // window and the one leaving it, in slot j % ZPF
+    float nw[ZPF][NC], od[ZPF][NC];
+    auto request = [&](int j, int sl) {
+        const int sn = clampi(z0 + j + RZ, a.nz) * pb, so = clampi(z0 + j - 1 - RZ, a.nz) * pb;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            nw[sl][q] = ld(mb, goff[q], sn);
+            od[sl][q] = ld(mb, goff[q], so);
+        }
+    };
+#pragma unroll
+    for (int k = 1; k <= ZPF; ++k) request(k, k % ZPF);
+
+    // y items: column c, rows run * YRUN .. + YRUN - 1
+    const bool yact = t < YI;
+    const int yc = t % ZTS, yrun = t / ZTS;
+    const int ox = x0 + yc;
+    const Rsrc yb = make_rsrc(a.ys, vb), fb = make_rsrc(a.f, vb);
+    int yoff[YRUN];
+#pragma unroll
+    for (int o = 0; o < YRUN; ++o) yoff[o] = (min(y0 + yrun * YRUN + o, a.ny - 1) * a.nx + min(ox, a.nx - 1)) * 4;
+    // x items: region row (fastest across lanes), run of output columns
+    const bool xact = t < XI;
+    const int xrow = t % W, xrun = t / W;
+
+    const int nout = z1 - z0;
+    for (int j0 = 0; j0 < nout; j0 += ZPF) {
+#pragma unroll
+        for (int jj = 0; jj < ZPF; ++jj) {
+            const int j = j0 + jj;
+            if (j >= nout) break;
+            const int z = z0 + j;
+            // the epilogue's Y values of this plane, consumed after both barriers
+            float yv[YRUN];
+#pragma unroll
+            for (int o = 0; o < YRUN; ++o) yv[o] = yact ? ld(yb, yoff[o], z * pb) : 0.0f;
+            if (j > 0) {
+#pragma unroll
+                for (int q = 0; q < NC; ++q) {
+                    const double vn = (double)nw[jj][q], vo = (double)od[jj][q];
+                    s1[q] += vn - vo;
+                    s2[q] += fma(vn, vn, -vo * vo);
+                }
+                request(j + ZPF, jj);
+            }
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+                if (cval[q]) zs[slot[q]] = make_double2(s1[q], s2[q]);
+            __syncthreads();
+            if (xact) {
+                const double2* src = zs + xrow * ZP + xrun * ZRUN;
+                double u1 = 0.0, u2 = 0.0;
+#pragma unroll
+                for (int k = 0; k <= 2 * R; ++k) {
+                    const double2 v = src[k];
+                    u1 += v.x;
+                    u2 += v.y;
+                }
+                double2* dst = xs + (xrun * ZRUN) * XP + xrow;
+                dst[0] = make_double2(u1, u2);
+#pragma unroll
+                for (int o = 1; o < ZRUN; ++o) {
+                    const double2 vi = src[o + 2 * R], vo = src[o - 1];
+                    u1 += vi.x - vo.x;
+                    u2 += vi.y - vo.y;
+                    dst[o * XP] = make_double2(u1, u2);
+                }
+            }
+            __syncthreads();
+            if (yact) {
+                const double2* src = xs + yc * XP + yrun * YRUN;
+                double u1 = 0.0, u2 = 0.0;
+#pragma unroll
+                for (int k = 0; k <= 2 * R; ++k) {
+                    const double2 v = src[k];
+                    u1 += v.x;
+                    u2 += v.y;
+                }
+#pragma unroll
+                for (int o = 0; o < YRUN; ++o) {
+                    if (o > 0) {
+                        const double2 vi = src[o + 2 * R], vo = src[o - 1];
+                        u1 += vi.x - vo.x;
+                        u2 += vi.y - vo.y;
+                    }
+                    const int oy = y0 + yrun * YRUN + o;
+                    if (ox < a.nx && oy < a.ny) {
+                        // I'_s = a S + b = E(M) + STD(M) (S - E(S)) / STD(S), combined
+                        // in FP64 and rounded once (a flat static patch: E(M) + S - E(S))
+                        const double mu = u1 * a.inv_n;
+                        double var = u2 * a.inv_n - mu * mu;
+                        var = var > 0.0 ? var : 0.0;
+                        const double c = (__float_as_uint(yv[o]) & 1u) ? 1.0 : (double)sqrtf((float)var);
+                        st(fb, yoff[o], z * pb, (float)fma(c, (double)yv[o], mu));
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int PZ>
+void launch_zf_one(const ZfArgs& a, hipStream_t st)
+{
+    constexpr int R = PZ / 2;
+    constexpr size_t lds = ZfLds<R>::BYTES;
+    static bool attr = false;
+    if (!attr && lds > 65536) {
+        (void)hipFuncSetAttribute((const void*)k_correct_zf<PZ, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_correct_zf<PZ, R>), dim3(a.nblocks), dim3(ZFT), lds, st, a);
+}
+
+}  // namespace
+
+bool correct_zf_applies(Dims d, const int patch[3])
+{
+    // (at 15^3 the region columns take 144 registers, one workgroup per CU:
+    // the x -> y -> z sweep is faster there, 232 against 319 us at 512^2 x 160)
+    const bool iso = patch[0] == patch[1] && patch[1] == patch[2] && patch[2] <= 13;
+    const long tiles = (long)((d.nx + ZTS - 1) / ZTS) * ((d.ny + ZTS - 1) / ZTS);
+    return iso && tiles * d.nz >= 4096;
+}
+
+hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, const int patch[3], hipStream_t st,
+                             const int* stop, int target)
+{
+    ZfArgs a{};
+    a.m = m;
+    a.ys = ys;
+    a.f = f;
+    a.stop = stop;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.inv_n = 1.0 / ((double)patch[0] * patch[1] * patch[2]);
+    a.tiles_x = (d.nx + ZTS - 1) / ZTS;
+    a.tiles_y = (d.ny + ZTS - 1) / ZTS;
+    const int tiles = a.tiles_x * a.tiles_y;
+    // about `target` workgroups (two per CU), chunks of at least 4 planes
+    int chunks = (target + tiles - 1) / tiles;
+    const int max_chunks = (d.nz + 3) / 4;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    a.zchunk = (d.nz + chunks - 1) / chunks;
+    chunks = (d.nz + a.zchunk - 1) / a.zchunk;
+    a.nblocks = tiles * chunks;
+    switch (patch[2]) {
+        case 1: launch_zf_one<1>(a, st); break;
+        case 3: launch_zf_one<3>(a, st); break;
+        case 5: launch_zf_one<5>(a, st); break;
+        case 7: launch_zf_one<7>(a, st); break;
+        case 9: launch_zf_one<9>(a, st); break;
+        case 11: launch_zf_one<11>(a, st); break;
+        case 13: launch_zf_one<13>(a, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace disc

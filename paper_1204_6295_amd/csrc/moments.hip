@@ -743,6 +743,8 @@ hipError_t launch_amed_values(const float* ct, const float* ys, const float* sd,
 hipError_t launch_correct(const float* m, const float* ys, float* f, Dims d, const int patch[3],
                           hipStream_t st, const int* stop)
 {
+    // isotropic patches on large volumes: the z-first sweep (correct_zf.hip)
+    if (correct_zf_applies(d, patch)) return launch_correct_zf(m, ys, f, d, patch, st, stop, 512);
     return launch_moments<kCorrect>(m, ys, f, nullptr, nullptr, d, patch, 0.0f, st, stop);
 }
 

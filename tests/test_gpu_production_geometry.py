@@ -165,3 +165,27 @@ def test_masked_iteration_whole_volume(disc, case):
     assert used >= 2
     assert mism == 0
     assert rel_err(f_g, f_ref) <= STEP_RTOL
+
+
+@pytest.mark.parametrize("patch", [(3, 3, 3), (11, 11, 11), (13, 13, 13), (15, 15, 15)])
+def test_correction_sweep_on_ragged_large_volume(disc, patch):
+    """The large-volume correction sweeps (the z-first sweep for isotropic
+    patches up to 13^3, the x -> y -> z sweep beyond; 32 x 32 tiles times
+    nz >= 4096 planes-tiles) on a volume ragged in x, y and z
+    (230 x 250 x 70: partial tiles on two sides, a short last z chunk), every
+    voxel against Eq. 3-6 in FP64, with a static image whose patches include
+    flat ones (constant blocks), so both epilogue branches run."""
+    g = np.random.default_rng([57, patch[0]])
+    shape = (70, 250, 230)
+    m = (g.normal(size=shape) * 200 + 40).astype(np.float32)
+    s = (0.8 * m + g.normal(size=shape) * 30 - 60).astype(np.float32)
+    s[10:40, 50:120, 60:150] = 35.0  # flat static region
+    md, sd = to_dev(m), to_dev(s)
+    ys = disc.static_stats(sd, patch)
+    f = to_np(disc.correct(md, ys, patch))
+    mu_m, var_m = oracle.patch_moments(m, patch)
+    mu_s, var_s = oracle.patch_moments(s, patch)
+    _, _, f_ref = oracle.correct(mu_m, var_m, mu_s, var_s, s)
+    e = rel_err(f, f_ref)
+    print("%s ragged 230x250x70: correction rel err %.3g" % (patch, e))
+    assert e <= STEP_RTOL
