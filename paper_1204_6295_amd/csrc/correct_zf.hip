@@ -48,7 +48,7 @@ struct ZfLds {
 };
 
 template <int PZ, int R>
-__global__ __launch_bounds__(ZFT) void k_correct_zf(ZfArgs a)
+__device__ __forceinline__ void zf_body(const ZfArgs& a, const int bid)
 {
     constexpr int RZ = PZ / 2;
     using L = ZfLds<R>;
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(ZFT) void k_correct_zf(ZfArgs a)
     double2* xs = zs + W * ZP;
     if (a.stop && *a.stop) return;  // the level has met its stopping rule
 
-    const int lb = xcd_logical_block(blockIdx.x, a.nblocks);
+    const int lb = xcd_logical_block(bid, a.nblocks);
     const int bx = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
     const int by = rest % a.tiles_y;
@@ -201,6 +201,51 @@ __global__ __launch_bounds__(ZFT) void k_correct_zf(ZfArgs a)
     }
 }
 
+template <int PZ, int R>
+__global__ __launch_bounds__(ZFT) void k_correct_zf(ZfArgs a)
+{
+    zf_body<PZ, R>(a, blockIdx.x);
+}
+
+template <int PZ, int R>
+__global__ __launch_bounds__(ZFT) void k_correct_zf_batch(Batch<ZfArgs> b)
+{
+    const int v = batch_volume(b.start, b.n, blockIdx.x);
+    zf_body<PZ, R>(b.v[v], blockIdx.x - b.start[v]);
+}
+
+// Tiles and z chunks for about `target` workgroups, chunks of at least 4 planes.
+void zf_grid(ZfArgs& a, Dims d, int target)
+{
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.tiles_x = (d.nx + ZTS - 1) / ZTS;
+    a.tiles_y = (d.ny + ZTS - 1) / ZTS;
+    const int tiles = a.tiles_x * a.tiles_y;
+    int chunks = (target + tiles - 1) / tiles;
+    const int max_chunks = (d.nz + 3) / 4;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    a.zchunk = (d.nz + chunks - 1) / chunks;
+    chunks = (d.nz + a.zchunk - 1) / a.zchunk;
+    a.nblocks = tiles * chunks;
+}
+
+template <int PZ>
+void launch_zf_batch_one(const Batch<ZfArgs>& b, hipStream_t st)
+{
+    constexpr int R = PZ / 2;
+    constexpr size_t lds = ZfLds<R>::BYTES;
+    static bool attr = false;
+    if (!attr && lds > 65536) {
+        (void)hipFuncSetAttribute((const void*)k_correct_zf_batch<PZ, R>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_correct_zf_batch<PZ, R>), dim3(b.start[b.n]), dim3(ZFT), lds, st, b);
+}
+
 template <int PZ>
 void launch_zf_one(const ZfArgs& a, hipStream_t st)
 {
@@ -234,21 +279,8 @@ hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, 
     a.ys = ys;
     a.f = f;
     a.stop = stop;
-    a.nx = d.nx;
-    a.ny = d.ny;
-    a.nz = d.nz;
     a.inv_n = 1.0 / ((double)patch[0] * patch[1] * patch[2]);
-    a.tiles_x = (d.nx + ZTS - 1) / ZTS;
-    a.tiles_y = (d.ny + ZTS - 1) / ZTS;
-    const int tiles = a.tiles_x * a.tiles_y;
-    // about `target` workgroups (two per CU), chunks of at least 4 planes
-    int chunks = (target + tiles - 1) / tiles;
-    const int max_chunks = (d.nz + 3) / 4;
-    if (chunks > max_chunks) chunks = max_chunks;
-    if (chunks < 1) chunks = 1;
-    a.zchunk = (d.nz + chunks - 1) / chunks;
-    chunks = (d.nz + a.zchunk - 1) / a.zchunk;
-    a.nblocks = tiles * chunks;
+    zf_grid(a, d, target);  // about `target` workgroups: two per CU
     switch (patch[2]) {
         case 1: launch_zf_one<1>(a, st); break;
         case 3: launch_zf_one<3>(a, st); break;
@@ -257,6 +289,44 @@ hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, 
         case 9: launch_zf_one<9>(a, st); break;
         case 11: launch_zf_one<11>(a, st); break;
         case 13: launch_zf_one<13>(a, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace disc
+
+namespace disc {
+
+bool correct_zf_batch_applies(const int patch[3])
+{
+    return patch[0] == patch[1] && patch[1] == patch[2] && patch[2] <= 13;
+}
+
+hipError_t launch_correct_zf_batch(const BatchVol* vols, int n, const int patch[3], int target, hipStream_t st)
+{
+    if (n < 1 || n > kMaxBatch) return hipErrorInvalidValue;
+    Batch<ZfArgs> b{};
+    b.n = n;
+    b.start[0] = 0;
+    for (int v = 0; v < n; ++v) {
+        ZfArgs& a = b.v[v];
+        a.m = vols[v].m;
+        a.ys = vols[v].ys;
+        a.f = vols[v].f;
+        a.stop = nullptr;
+        a.inv_n = 1.0 / ((double)patch[0] * patch[1] * patch[2]);
+        zf_grid(a, vols[v].d, target);
+        b.start[v + 1] = b.start[v] + a.nblocks;
+    }
+    switch (patch[2]) {
+        case 1: launch_zf_batch_one<1>(b, st); break;
+        case 3: launch_zf_batch_one<3>(b, st); break;
+        case 5: launch_zf_batch_one<5>(b, st); break;
+        case 7: launch_zf_batch_one<7>(b, st); break;
+        case 9: launch_zf_batch_one<9>(b, st); break;
+        case 11: launch_zf_batch_one<11>(b, st); break;
+        case 13: launch_zf_batch_one<13>(b, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

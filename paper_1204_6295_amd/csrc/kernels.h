@@ -111,6 +111,10 @@ bool correct_zf_applies(Dims d, const int patch[3]);
 hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, const int patch[3], hipStream_t st,
                              const int* stop, int target);
 
+struct BatchVol;
+bool correct_zf_batch_applies(const int patch[3]);
+hipError_t launch_correct_zf_batch(const BatchVol* vols, int n, const int patch[3], int target, hipStream_t st);
+
 // Global shift: FP64 partial sums, then s = cbct + (mean ct - mean cbct).
 size_t shift_scratch_bytes();
 hipError_t launch_shift(const float* ct, const float* cbct, long n, float* s, double* dhu,

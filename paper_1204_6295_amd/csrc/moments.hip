@@ -763,6 +763,10 @@ hipError_t launch_correct_batch(const BatchVol* vols, int n, const int patch[3],
                                 hipStream_t st)
 {
     if (n < 1 || n > kMaxBatch || (tiles.mom_ts != 16 && tiles.mom_ts != 32)) return hipErrorInvalidValue;
+    // 32 x 32 tiles and an isotropic patch: the z-first sweep, two 512-thread
+    // workgroups for every 1024-thread one of mom_target
+    if (tiles.mom_ts == 32 && correct_zf_batch_applies(patch))
+        return launch_correct_zf_batch(vols, n, patch, 2 * tiles.mom_target, st);
     Batch<MomArgs> b{};
     b.n = n;
     b.start[0] = 0;
