@@ -381,12 +381,28 @@ __device__ __forceinline__ void smooth_z_body(const ZArgs& a, const int bid)
 {
     constexpr int K = 2 * R + 1;
     if (a.stop && *a.stop) return;  // the level has met its stopping rule
-    const int col0 = (bid % a.colblocks) * ZNT + (int)threadIdx.x;
+    // block -> (column block, chunk): workgroups are dealt round-robin over
+    // the 8 XCDs; XCD k takes the contiguous column blocks [kG, kG + G), one
+    // chunk after the other, so the halo planes neighbouring chunks share and
+    // the CT rows the warp gathers around neighbouring rows of the volume are
+    // both re-read from that XCD's L2 (blocks past the end are idle)
+    const int G = (a.colblocks + 7) / 8;
+    const int nch = (a.nz + a.zchunk - 1) / a.zchunk;
+    const int xcd = bid & 7, local = bid >> 3;
+    const int cblk = xcd * G + local % G, chunk = local / G;
+    if (cblk >= a.colblocks || chunk >= nch) {
+        if (NORM && threadIdx.x == 0) {
+            a.norms[2 * bid] = 0.0;
+            a.norms[2 * bid + 1] = 0.0;
+        }
+        return;
+    }
+    const int col0 = cblk * ZNT + (int)threadIdx.x;
     if (!NORM && col0 >= (int)a.ncols) return;
     const bool act = col0 < (int)a.ncols;
     const int col = act ? col0 : (int)a.ncols - 1;  // idle lanes (NORM) read a valid column
     const int xcol = col % a.nx, ycol = col / a.nx;
-    const int z0 = (bid / a.colblocks) * a.zchunk;
+    const int z0 = chunk * a.zchunk;
     const int z1 = min(a.nz, z0 + a.zchunk);
     // buffer access: the lane's column is the per-lane byte offset, the plane
     // a scalar offset; each field component has its own resource
@@ -497,8 +513,12 @@ __global__ __launch_bounds__(ZNT) void k_smooth_z_direct(ZArgs a)
 {
     constexpr int K = 2 * R + 1;
     if (a.stop && *a.stop) return;  // the level has met its stopping rule
-    const int col = (blockIdx.x % a.colblocks) * ZNT + (int)threadIdx.x;
-    const int z = blockIdx.x / a.colblocks;
+    // the block order of smooth_z_body with one-plane chunks
+    const int G = (a.colblocks + 7) / 8;
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int cblk = xcd * G + local % G, z = local / G;
+    if (cblk >= a.colblocks || z >= a.nz) return;
+    const int col = cblk * ZNT + (int)threadIdx.x;
     if (col >= (int)a.ncols) return;
     const int pb = a.nx * a.ny * 4;
     const long N = (long)a.nx * a.ny * a.nz;
@@ -616,7 +636,8 @@ ZArgs z_args(const float* q, float* out, Dims d, const GaussTaps& t, int target 
 
 int z_blocks(const ZArgs& a)
 {
-    return a.colblocks * ((a.nz + a.zchunk - 1) / a.zchunk);
+    // (column blocks padded to a multiple of 8, see smooth_z_body)
+    return 8 * ((a.colblocks + 7) / 8) * ((a.nz + a.zchunk - 1) / a.zchunk);
 }
 
 hipError_t launch_z(const float* q, float* out, Dims d, const GaussTaps& t, const int* stop, double* norms,
