@@ -15,6 +15,7 @@
 // The x and y passes run only on output planes (the z halo costs one add
 // per column and plane), and the workgroup's 51 KB of LDS lets two of them
 // share a CU, so one workgroup's barrier waits overlap the other's work.
+// Used for isotropic patches up to 13^3 at every volume size.
 #include <cmath>
 
 #include "kernels.h"
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(ZFT) void k_correct_zf_batch(Batch<ZfArgs> b)
     zf_body<PZ, R>(b.v[v], blockIdx.x - b.start[v]);
 }
 
-// Tiles and z chunks for about `target` workgroups, chunks of at least 4 planes.
+// Tiles and z chunks for about `target` workgroups.
 void zf_grid(ZfArgs& a, Dims d, int target)
 {
     a.nx = d.nx;
@@ -224,8 +225,7 @@ void zf_grid(ZfArgs& a, Dims d, int target)
     a.tiles_y = (d.ny + ZTS - 1) / ZTS;
     const int tiles = a.tiles_x * a.tiles_y;
     int chunks = (target + tiles - 1) / tiles;
-    const int max_chunks = (d.nz + 3) / 4;
-    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks > d.nz) chunks = d.nz;
     if (chunks < 1) chunks = 1;
     a.zchunk = (d.nz + chunks - 1) / chunks;
     chunks = (d.nz + a.zchunk - 1) / a.zchunk;
@@ -266,9 +266,8 @@ bool correct_zf_applies(Dims d, const int patch[3])
 {
     // (at 15^3 the region columns take 144 registers, one workgroup per CU:
     // the x -> y -> z sweep is faster there, 232 against 319 us at 512^2 x 160)
-    const bool iso = patch[0] == patch[1] && patch[1] == patch[2] && patch[2] <= 13;
-    const long tiles = (long)((d.nx + ZTS - 1) / ZTS) * ((d.ny + ZTS - 1) / ZTS);
-    return iso && tiles * d.nz >= 4096;
+    (void)d;
+    return patch[0] == patch[1] && patch[1] == patch[2] && patch[2] <= 13;
 }
 
 hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, const int patch[3], hipStream_t st,
@@ -280,7 +279,7 @@ hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, 
     a.f = f;
     a.stop = stop;
     a.inv_n = 1.0 / ((double)patch[0] * patch[1] * patch[2]);
-    zf_grid(a, d, target);  // about `target` workgroups: two per CU
+    zf_grid(a, d, target);
     switch (patch[2]) {
         case 1: launch_zf_one<1>(a, st); break;
         case 3: launch_zf_one<3>(a, st); break;

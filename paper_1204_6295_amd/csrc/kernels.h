@@ -105,7 +105,7 @@ size_t median_scratch_bytes();
 hipError_t launch_mask_consts(const float* a_vals, long n, const double* dhu, float hu0, float lo_frac,
                               float hi_frac, float h, void* scratch, float* consts, hipStream_t st);
 
-// Moments + correction, z first (isotropic patches on large volumes; about
+// Moments + correction, z first (isotropic patches up to 13^3; about
 // `target` workgroups of 512 threads).
 bool correct_zf_applies(Dims d, const int patch[3]);
 hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, const int patch[3], hipStream_t st,
