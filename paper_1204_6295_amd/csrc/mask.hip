@@ -524,6 +524,11 @@ int fill_tiles(Dims d)
 
 namespace {
 
+// Static LDS of k_fill_list (count, bb, part, dmins, zxa): the dynamic
+// region must fit beside it in the default 64 KiB per workgroup.
+constexpr size_t kFillStaticLds = sizeof(int) + 4 * sizeof(int) + FTX * FTY * sizeof(double3) +
+                                  FTX * FTY * sizeof(float) + (FTY + 2 * 7) * FTX;
+
 // the work-list kernels take a region row per wave (RW <= 64) and one
 // neighbouring tile per thread when queueing
 bool fill_lists_fit(const int t[3], size_t* lds)
@@ -532,7 +537,8 @@ bool fill_lists_fit(const int t[3], size_t* lds)
     const size_t plane = (size_t)(FTX + 2 * tx) * (FTY + 2 * ty), nreg = plane * (2 * tz + 1);
     *lds = nreg * sizeof(float4) + ((nreg + plane + 3) & ~(size_t)3) + FTX * FTY * sizeof(int);
     const int reach = 3 * 3 * (2 * tz + 1);
-    return *lds <= 64 * 1024 && FTX + 2 * tx <= 64 && tx < FTX && ty < FTY && reach <= FTX * FTY;
+    return *lds + kFillStaticLds <= 64 * 1024 && FTX + 2 * tx <= 64 && tx < FTX && ty < FTY &&
+           reach <= FTX * FTY;
 }
 
 FillQ make_q(const FillLists& fl, Dims d, const int t[3])

@@ -3,8 +3,12 @@
 At set-up the device resolves the Sec. 2.3 rules (a_m, HU_0, h); one
 iteration from r = 0 then exercises the mask and every fill pass on known
 inputs (m = CT exactly), and whole registrations compare fields. Mask
-decisions are taken on FP32 data on both sides; the inputs keep every
-voxel's |m - S| and a away from the thresholds by much more than rounding.
+decisions are taken on FP32 data on the GPU and in FP64 by the oracle: the
+per-region fill cases accept either decision for voxels within FP32
+rounding of HU_0 or of a_min / a_max, require the oracle's decision
+everywhere else, and then compare the fill pass by pass from the GPU's own
+mask; the whole-registration cases use inputs whose |m - S| and a stay far
+from the thresholds.
 """
 import numpy as np
 import pytest
@@ -75,11 +79,17 @@ def test_first_iteration_mask_and_fill(disc):
     ((12, 40, 36), (15, 15, 9), 3),  # T region too large for LDS: gathers from cache
     ((48, 128, 128), (7, 7, 3), 10),  # 3072 fill tiles
     ((40, 256, 256), (7, 7, 3), 10),  # 10240 fill tiles, more than the workgroups of a pass
+    ((20, 45, 70), (13, 7, 5), 4),  # work-list kernel with its LDS just under the 64 KiB limit
+    ((20, 45, 70), (13, 9, 5), 4),  # just over it: the cache-gather kernel
 ])
 def test_fill_passes_and_regions(disc, shape, t, passes):
     """One iteration from r = 0 for several T regions and pass counts, on
     volumes with ragged tiles: the pass structure (which voxels each pass
-    fills, and from what) must equal the oracle's."""
+    fills, and from what) must equal the oracle's. The GPU's Eq. 7 mask is
+    checked against the oracle's decision (voxels within FP32 rounding of a
+    threshold may take either side), then the oracle fills from the GPU's
+    mask and the pass map (disc_get_mask: 0 valid, p filled by pass p, 255
+    never filled) must be identical voxel for voxel."""
     from synth.phantom import make_hn_pair
 
     if shape == (48, 48, 48):
@@ -107,6 +117,19 @@ def test_fill_passes_and_regions(disc, shape, t, passes):
     if t == (1, 1, 1):
         assert used == 0
     assert rel_err(f, f_ref) <= 1e-4
+    # the pass map, filled by the oracle from the GPU's own mask
+    stamp = to_np(reg.mask())
+    ctd = ct.astype(np.float64)
+    mu_m, var_m = oracle.patch_moments(ctd, (5, 5, 5))
+    mu_s, var_s = oracle.patch_moments(s32, (5, 5, 5))
+    a0, b0, _ = oracle.correct(mu_m, var_m, mu_s, var_s, s32)
+    dm = np.abs(ctd - s32) - mp["hu0"]
+    near = (np.abs(dm) <= 1e-3) | (np.abs(a0 - mp["a_min"]) <= 1e-5 * mp["a_min"]) | \
+        (np.abs(a0 - mp["a_max"]) <= 1e-5 * mp["a_max"])
+    xi_gpu = stamp != 0
+    assert not ((xi_gpu != xi) & ~near).any()
+    _, _, used2, pass_of = oracle.fill_ex(a0, b0, ~xi_gpu, s32, mp["h"], t=t, passes=passes)
+    assert np.array_equal(pass_of, stamp), "pass maps differ at %d voxels" % int((pass_of != stamp).sum())
 
 
 def test_masked_registration_matches_oracle(disc):
