@@ -13,8 +13,9 @@
 //   y pass  sliding sums along y, 2 outputs per item (one item per
 //           thread), then the epilogue I'_s = E(M) + STD(M) Y at those voxels.
 // The x and y passes run only on output planes (the z halo costs one add
-// per column and plane), and the workgroup's 51 KB of LDS lets two of them
-// share a CU, so one workgroup's barrier waits overlap the other's work.
+// per column and plane). The kernel is held to 80 VGPRs (six waves per
+// SIMD), so with its 51 KB of LDS at 11^3 three workgroups share a CU and
+// one workgroup's barrier waits overlap the others' work.
 // Used for isotropic patches up to 13^3 at every volume size.
 #include <cmath>
 
@@ -28,7 +29,7 @@ constexpr int ZTS = 32;   // output tile edge
 constexpr int ZFT = 512;  // threads per workgroup
 constexpr int ZRUN = 4;   // outputs per x item
 constexpr int YRUN = 2;   // outputs per y item (every thread takes one)
-constexpr int ZPF = 2;    // steps of m loads in flight
+constexpr int ZPF = 1;    // steps of m loads in flight (two would not fit in 80 VGPRs)
 
 struct ZfArgs {
     const float* m;    // deformed moving image
@@ -203,13 +204,13 @@ __device__ __forceinline__ void zf_body(const ZfArgs& a, const int bid)
 }
 
 template <int PZ, int R>
-__global__ __launch_bounds__(ZFT) void k_correct_zf(ZfArgs a)
+__global__ __launch_bounds__(ZFT, 6) void k_correct_zf(ZfArgs a)
 {
     zf_body<PZ, R>(a, blockIdx.x);
 }
 
 template <int PZ, int R>
-__global__ __launch_bounds__(ZFT) void k_correct_zf_batch(Batch<ZfArgs> b)
+__global__ __launch_bounds__(ZFT, 6) void k_correct_zf_batch(Batch<ZfArgs> b)
 {
     const int v = batch_volume(b.start, b.n, blockIdx.x);
     zf_body<PZ, R>(b.v[v], blockIdx.x - b.start[v]);
@@ -261,6 +262,24 @@ void launch_zf_one(const ZfArgs& a, hipStream_t st)
 }
 
 }  // namespace
+
+int correct_zf_resident(const int patch[3])
+{
+    // workgroups per CU: 160 KB of LDS and six 80-VGPR waves per SIMD (three
+    // 8-wave workgroups)
+    size_t lds = 0;
+    switch (patch[2]) {
+        case 1: lds = ZfLds<0>::BYTES; break;
+        case 3: lds = ZfLds<1>::BYTES; break;
+        case 5: lds = ZfLds<2>::BYTES; break;
+        case 7: lds = ZfLds<3>::BYTES; break;
+        case 9: lds = ZfLds<4>::BYTES; break;
+        case 11: lds = ZfLds<5>::BYTES; break;
+        default: lds = ZfLds<6>::BYTES; break;
+    }
+    const int by_lds = (int)((160 * 1024) / lds);
+    return by_lds < 3 ? by_lds : 3;
+}
 
 bool correct_zf_applies(Dims d, const int patch[3])
 {

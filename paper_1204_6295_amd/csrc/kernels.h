@@ -108,6 +108,7 @@ hipError_t launch_mask_consts(const float* a_vals, long n, const double* dhu, fl
 // Moments + correction, z first (isotropic patches up to 13^3; about
 // `target` workgroups of 512 threads).
 bool correct_zf_applies(Dims d, const int patch[3]);
+int correct_zf_resident(const int patch[3]);  // workgroups of the sweep per CU
 hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, const int patch[3], hipStream_t st,
                              const int* stop, int target);
 

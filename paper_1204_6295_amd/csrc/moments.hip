@@ -743,12 +743,14 @@ hipError_t launch_amed_values(const float* ct, const float* ys, const float* sd,
 hipError_t launch_correct(const float* m, const float* ys, float* f, Dims d, const int patch[3],
                           hipStream_t st, const int* stop)
 {
-    // isotropic patches: the z-first sweep (correct_zf.hip), about two
-    // 512-thread workgroups per CU on large volumes (256 x 256 x 96: 512
-    // measured best), 256 on small ones (128 x 128 x 48: 11 against 13 us)
+    // isotropic patches: the z-first sweep (correct_zf.hip), one round of
+    // resident 512-thread workgroups on large volumes (three per CU at 11^3:
+    // 32.8 against 35.3 us at 256 x 256 x 96 with two), 256 on small ones
+    // (128 x 128 x 48: 11 against 13 us)
     if (correct_zf_applies(d, patch)) {
         const long t32 = (long)((d.nx + 31) / 32) * ((d.ny + 31) / 32);
-        return launch_correct_zf(m, ys, f, d, patch, st, stop, t32 * d.nz >= 4096 ? 512 : 256);
+        return launch_correct_zf(m, ys, f, d, patch, st, stop,
+                                 t32 * d.nz >= 4096 ? 256 * correct_zf_resident(patch) : 256);
     }
     return launch_moments<kCorrect>(m, ys, f, nullptr, nullptr, d, patch, 0.0f, st, stop);
 }

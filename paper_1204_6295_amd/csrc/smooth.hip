@@ -6,7 +6,7 @@
 //               (R = ceil(3 sigma)), u being the Eq. 1 demons force on the
 //               corrected image f (the f plane is staged in LDS for the
 //               in-plane gradient), then runs the x and y passes out of LDS
-//               with register-blocked runs of 4 outputs and writes the
+//               with register-blocked runs of 8 (x) and 4 (y) outputs and writes the
 //               xy-filtered field q; the four stages are software-pipelined
 //               over planes.
 //   k_smooth_z  one thread per (x, y) column over a chunk of z: a register
@@ -24,7 +24,11 @@ namespace disc {
 
 namespace {
 
-constexpr int SRUN = 4;
+constexpr int SRUN = 4;  // outputs per y-pass item
+// outputs per x-pass item (a multiple of 4): 3 x 44 rows x 4 items fit one
+// pass of the 1024 threads at R = 6, where runs of 4 need 1056 items
+// (force + xy 53.4 against 54.2 us at 256 x 256 x 96)
+constexpr int XRUN = 8;
 
 struct PlaneArgs {
     const float* m;    // deformed moving image (force mode)
@@ -70,7 +74,7 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
     constexpr int K = 2 * R + 1;
     using L = PipeLds<R, FM>;
     constexpr int W = L::W, PW = L::PW, H = L::H, FW = L::FW, FH = L::FH;
-    constexpr int XITEMS = 3 * H * (QTX / SRUN);
+    constexpr int XITEMS = 3 * H * (QTX / XRUN);
     constexpr int YITEMS = 3 * QTX * (QTY / SRUN);
     constexpr int NF = FORCE ? (FH * FW + NT - 1) / NT : 1;
     constexpr int NP = (H * W + NT - 1) / NT;
@@ -252,32 +256,35 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
             }
         }
         fetch_points(cur, ps + 1);
-        // x pass of plane s - 2: 4 consecutive outputs of one row per item
+        // x pass of plane s - 2: XRUN consecutive outputs of one row per item
         if (px >= 0 && px < nplanes) {
             const float* sin = s_in0 + par * (3 * H * PW);
             float* sx = s_x0 + par * (3 * H * QTX);
             for (int i = t; i < XITEMS; i += NT) {
-                const int run = i % (QTX / SRUN), cr = i / (QTX / SRUN);
+                const int run = i % (QTX / XRUN), cr = i / (QTX / XRUN);
                 const int c = cr / H, row = cr - c * H;
-                const float* src = sin + (c * H + row) * PW + run * SRUN;
-                float v[(SRUN + 2 * R + 3) & ~3];
+                const float* src = sin + (c * H + row) * PW + run * XRUN;
+                float v[(XRUN + 2 * R + 3) & ~3];
 #pragma unroll
-                for (int j = 0; j < (SRUN + 2 * R + 3) / 4; ++j) {
+                for (int j = 0; j < (XRUN + 2 * R + 3) / 4; ++j) {
                     const float4 w4 = *reinterpret_cast<const float4*>(src + 4 * j);
                     v[4 * j] = w4.x;
                     v[4 * j + 1] = w4.y;
                     v[4 * j + 2] = w4.z;
                     v[4 * j + 3] = w4.w;
                 }
-                float o[SRUN];
+                float o[XRUN];
 #pragma unroll
-                for (int rr = 0; rr < SRUN; ++rr) {
+                for (int rr = 0; rr < XRUN; ++rr) {
                     float sacc = 0.0f;
 #pragma unroll
                     for (int j = 0; j < K; ++j) sacc = fmaf(a.taps.w[j], v[rr + j], sacc);
                     o[rr] = sacc;
                 }
-                *reinterpret_cast<float4*>(sx + (c * H + row) * QTX + run * SRUN) = make_float4(o[0], o[1], o[2], o[3]);
+#pragma unroll
+                for (int g = 0; g < XRUN / 4; ++g)
+                    *reinterpret_cast<float4*>(sx + (c * H + row) * QTX + run * XRUN + 4 * g) =
+                        make_float4(o[4 * g], o[4 * g + 1], o[4 * g + 2], o[4 * g + 3]);
             }
         }
         // y pass of plane s - 3: 4 consecutive outputs of one column per item, to q
