@@ -746,23 +746,18 @@ struct SsdScratch {
     size_t bytes;
 };
 
+// (base may be null: sizes only)
 SsdScratch ssd_carve(char* base, Dims d)
 {
-    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t n = (size_t)d.n();
+    Carver cv{base};
     SsdScratch s;
-    size_t off = 0;
-    s.m = reinterpret_cast<float*>(base + off);
-    off += up(n * sizeof(float));
-    s.dres = reinterpret_cast<float*>(base + off);
-    off += up(n * sizeof(float));
-    s.a = reinterpret_cast<double2*>(base + off);
-    off += up(n * sizeof(double2));
-    s.b = reinterpret_cast<double2*>(base + off);
-    off += up(n * sizeof(double2));
-    s.partial = reinterpret_cast<double*>(base + off);
-    off += up((size_t)disc::ssd_partial_count(d) * sizeof(double));
-    s.bytes = off;
+    s.m = static_cast<float*>(cv.take(n * sizeof(float)));
+    s.dres = static_cast<float*>(cv.take(n * sizeof(float)));
+    s.a = static_cast<double2*>(cv.take(n * sizeof(double2)));
+    s.b = static_cast<double2*>(cv.take(n * sizeof(double2)));
+    s.partial = static_cast<double*>(cv.take((size_t)disc::ssd_partial_count(d) * sizeof(double)));
+    s.bytes = (cv.off + 255) & ~(size_t)255;
     return s;
 }
 
