@@ -5,7 +5,7 @@
 // planes. Every column of the tile plus its in-plane patch halo keeps the
 // FP64 sums of m and m^2 over its z window in registers, advanced by one
 // plane per step (add the plane entering the window, subtract the one
-// leaving it; both loads are requested two steps ahead). Per output plane:
+// leaving it; both loads are requested one step ahead). Per output plane:
 //   store   the column sums in LDS;                         barrier
 //   x pass  sliding sums along x of those, 4 outputs per item, one lane per
 //           region row (row-fastest lanes: conflict-free 16-byte accesses);
@@ -27,7 +27,7 @@ namespace {
 
 constexpr int ZTS = 32;   // output tile edge
 constexpr int ZFT = 512;  // threads per workgroup
-constexpr int ZRUN = 4;   // outputs per x item
+constexpr int XRUN = 4;   // outputs per x item
 constexpr int YRUN = 2;   // outputs per y item (every thread takes one)
 constexpr int ZPF = 1;    // steps of m loads in flight (two would not fit in 80 VGPRs)
 
@@ -56,7 +56,7 @@ __device__ __forceinline__ void zf_body(const ZfArgs& a, const int bid)
     using L = ZfLds<R>;
     constexpr int W = L::W, ZP = L::ZP, XP = L::XP;
     constexpr int NC = (W * W + ZFT - 1) / ZFT;  // region columns per thread
-    constexpr int XI = W * (ZTS / ZRUN);          // x items
+    constexpr int XI = W * (ZTS / XRUN);          // x items
     constexpr int YI = ZTS * (ZTS / YRUN);        // y items
     static_assert(XI <= ZFT && YI <= ZFT, "one x and one y item per thread");
     extern __shared__ __align__(16) unsigned char smem[];
@@ -152,7 +152,7 @@ __device__ __forceinline__ void zf_body(const ZfArgs& a, const int bid)
                 if (cval[q]) zs[slot[q]] = make_double2(s1[q], s2[q]);
             __syncthreads();
             if (xact) {
-                const double2* src = zs + xrow * ZP + xrun * ZRUN;
+                const double2* src = zs + xrow * ZP + xrun * XRUN;
                 double u1 = 0.0, u2 = 0.0;
 #pragma unroll
                 for (int k = 0; k <= 2 * R; ++k) {
@@ -160,10 +160,10 @@ __device__ __forceinline__ void zf_body(const ZfArgs& a, const int bid)
                     u1 += v.x;
                     u2 += v.y;
                 }
-                double2* dst = xs + (xrun * ZRUN) * XP + xrow;
+                double2* dst = xs + (xrun * XRUN) * XP + xrow;
                 dst[0] = make_double2(u1, u2);
 #pragma unroll
-                for (int o = 1; o < ZRUN; ++o) {
+                for (int o = 1; o < XRUN; ++o) {
                     const double2 vi = src[o + 2 * R], vo = src[o - 1];
                     u1 += vi.x - vo.x;
                     u2 += vi.y - vo.y;
