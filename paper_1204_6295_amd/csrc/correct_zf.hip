@@ -238,12 +238,7 @@ void launch_zf_batch_one(const Batch<ZfArgs>& b, hipStream_t st)
 {
     constexpr int R = PZ / 2;
     constexpr size_t lds = ZfLds<R>::BYTES;
-    static bool attr = false;
-    if (!attr && lds > 65536) {
-        (void)hipFuncSetAttribute((const void*)k_correct_zf_batch<PZ, R>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    lds_limit((const void*)k_correct_zf_batch<PZ, R>, lds);
     hipLaunchKernelGGL((k_correct_zf_batch<PZ, R>), dim3(b.start[b.n]), dim3(ZFT), lds, st, b);
 }
 
@@ -252,12 +247,7 @@ void launch_zf_one(const ZfArgs& a, hipStream_t st)
 {
     constexpr int R = PZ / 2;
     constexpr size_t lds = ZfLds<R>::BYTES;
-    static bool attr = false;
-    if (!attr && lds > 65536) {
-        (void)hipFuncSetAttribute((const void*)k_correct_zf<PZ, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-        attr = true;
-    }
+    lds_limit((const void*)k_correct_zf<PZ, R>, lds);
     hipLaunchKernelGGL((k_correct_zf<PZ, R>), dim3(a.nblocks), dim3(ZFT), lds, st, a);
 }
 

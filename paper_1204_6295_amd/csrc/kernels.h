@@ -12,6 +12,11 @@
 
 namespace disc {
 
+// Raises `kernel`'s dynamic-LDS limit to `bytes` on the current device when
+// that is above the 64 KB default, once per kernel and device (thread-safe).
+// The following launch reports any failure.
+void lds_limit(const void* kernel, size_t bytes);
+
 // Builds taps exp(-k^2 / 2 sigma^2), |k| <= ceil(3 sigma), normalised in FP64.
 // Returns false when sigma is outside (0, kMaxGaussR / 3].
 bool make_gauss_taps(float sigma, GaussTaps* t);

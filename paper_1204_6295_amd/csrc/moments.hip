@@ -527,12 +527,7 @@ void launch_pp_kernel(const MomArgs& a, hipStream_t st)
 {
     constexpr size_t lds = PpLds<PZ, PZ / 2>::BYTES;
     static_assert(lds <= 160 * 1024, "fits the LDS of one CU");
-    static bool attr = false;
-    if (!attr && lds > 65536) {
-        (void)hipFuncSetAttribute((const void*)k_moments_pp<PZ, PZ / 2, MODE>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    lds_limit((const void*)k_moments_pp<PZ, PZ / 2, MODE>, lds);
     hipLaunchKernelGGL((k_moments_pp<PZ, PZ / 2, MODE>), dim3(a.nblocks), dim3(PPS * PG), lds, st, a);
 }
 
@@ -554,12 +549,7 @@ void launch_kernel(const MomArgs& a, hipStream_t st)
 {
     constexpr size_t lds = MomLds<RXY, TS>::BYTES;
     static_assert(lds >= TS * TS * sizeof(double), "room for the loss reduction");
-    static bool attr = false;  // raise the dynamic LDS limit once per instantiation
-    if (!attr && lds > 65536) {
-        (void)hipFuncSetAttribute((const void*)k_moments<PZ, RXY, MODE, TS>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    lds_limit((const void*)k_moments<PZ, RXY, MODE, TS>, lds);
     hipLaunchKernelGGL((k_moments<PZ, RXY, MODE, TS>), dim3(a.nblocks), dim3(TS * TS), lds, st, a);
 }
 
@@ -679,12 +669,7 @@ template <int PZ, int RXY, int TS>
 void launch_batch_kernel(const Batch<MomArgs>& b, hipStream_t st)
 {
     constexpr size_t lds = MomLds<RXY, TS>::BYTES;
-    static bool attr = false;
-    if (!attr && lds > 65536) {
-        (void)hipFuncSetAttribute((const void*)k_moments_batch<PZ, RXY, kCorrect, TS>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    lds_limit((const void*)k_moments_batch<PZ, RXY, kCorrect, TS>, lds);
     hipLaunchKernelGGL((k_moments_batch<PZ, RXY, kCorrect, TS>), dim3(b.start[b.n]), dim3(TS * TS), lds,
                        st, b);
 }

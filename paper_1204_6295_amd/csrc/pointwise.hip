@@ -7,6 +7,9 @@
 // 256-byte wave access; warp-corner gathers hit the same or adjacent cache
 // lines.
 #include <cmath>
+#include <mutex>
+#include <set>
+#include <utility>
 
 #include "kernels.h"
 
@@ -321,6 +324,19 @@ hipError_t launch_shift(const float* ct, const float* cbct, long n, float* s, do
     hipLaunchKernelGGL(k_shift_finish, dim3(1), dim3(256), 0, st, part, n, d);
     hipLaunchKernelGGL(k_shift_apply, dim3(blocks_for(n, 256 * 8)), dim3(256), 0, st, cbct, n, d, s);
     return hipGetLastError();
+}
+
+void lds_limit(const void* kernel, size_t bytes)
+{
+    if (bytes <= 65536) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    static std::mutex mu;
+    static std::set<std::pair<const void*, int>> done;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({kernel, dev})) return;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        done.insert({kernel, dev});
 }
 
 }  // namespace disc

@@ -334,22 +334,11 @@ __global__ __launch_bounds__(QTX* QTY) void k_plane_pipe_batch(Batch<PlaneArgs> 
     plane_pipe_body<R, FM>(b.v[v], blockIdx.x - b.start[v]);
 }
 
-// Raises the dynamic LDS limit of a kernel once (first launch).
-template <class F>
-void lds_attr_once(F* kernel, size_t bytes, bool& done)
-{
-    if (!done && bytes > 65536) {
-        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        done = true;
-    }
-}
-
 template <int R, int FM>
 void launch_pipe_one(const PlaneArgs& a, hipStream_t st)
 {
     constexpr size_t lds = PipeLds<R, FM>::BYTES;
-    static bool done = false;
-    lds_attr_once(k_plane_pipe<R, FM>, lds, done);
+    lds_limit((const void*)k_plane_pipe<R, FM>, lds);
     hipLaunchKernelGGL((k_plane_pipe<R, FM>), dim3(a.nblocks), dim3(QTX * QTY), lds, st, a);
 }
 
@@ -357,8 +346,7 @@ template <int R, int FM>
 void launch_pipe_batch_one(const Batch<PlaneArgs>& b, hipStream_t st)
 {
     constexpr size_t lds = PipeLds<R, FM>::BYTES;
-    static bool done = false;
-    lds_attr_once(k_plane_pipe_batch<R, FM>, lds, done);
+    lds_limit((const void*)k_plane_pipe_batch<R, FM>, lds);
     hipLaunchKernelGGL((k_plane_pipe_batch<R, FM>), dim3(b.start[b.n]), dim3(QTX * QTY), lds, st, b);
 }
 
