@@ -46,12 +46,18 @@ struct PlaneArgs {
 
 // ---- force + xy smoothing, software-pipelined over planes ------------------
 // FM: 0 smoothing only, 1 Eq. 1 static-gradient force, 2 both Eq. 1 terms.
-// A workgroup owns a 32 x 32 column tile and a z chunk. Four stages per plane: stash the f (and m) region in LDS; form r~ = r - u
-// on the tile plus halo; the x pass; the y pass into q. Step s runs the
-// stash of plane s, the force of plane s-1, the x pass of plane s-2 and the
-// y pass of plane s-3 against double-buffered LDS, so one barrier per plane
-// separates them and no stage waits for another. Global loads run ahead: the
-// f region of plane s+1 and the per-point data of plane s+1 are requested in
+// A workgroup owns a 32 x 32 column tile and a z chunk. Four stages per
+// plane: stash the f (and m) region in LDS; form r~ = r - u on the tile
+// plus halo; the x pass; the y pass into q. Step s runs the stash of the f
+// region of plane s+1 (the m region of plane s), the force of plane s-1,
+// the x pass of plane s-2 and the y pass of plane s-3, so one barrier per
+// plane separates them and no stage waits for another. The f regions sit in
+// four LDS slots, so the force reads the z neighbours of f (planes s-2 and
+// s) from LDS as it reads the in-plane ones: f is fetched from memory once
+// per plane (at 512 x 512 x 160, where the working set is far beyond the
+// Infinity Cache, re-reading them per point cost 16 % of the kernel). The
+// other LDS buffers are double-buffered. Global loads run ahead: the f
+// region of plane s+2 and the per-point data of plane s+1 are requested in
 // step s (the per-point data is consumed in step s+2, hence two register
 // sets and steps taken in pairs).
 constexpr int QTX = 32, QTY = 32;
@@ -63,7 +69,10 @@ struct PipeLds {
     static constexpr size_t F_BYTES = (size_t)FH * FW * sizeof(float);
     static constexpr size_t IN_BYTES = (size_t)3 * H * PW * sizeof(float);
     static constexpr size_t X_BYTES = (size_t)3 * H * QTX * sizeof(float);
-    static constexpr size_t BYTES = 2 * (F_BYTES * (FM == 2 ? 2 : 1) + IN_BYTES + X_BYTES);
+    // f: four plane slots (z - 1, z, z + 1 of the plane whose force is formed, and
+    // the one being stashed); m (double force): two
+    static constexpr int F_SLOTS = FM > 0 ? 4 : 0, M_SLOTS = FM == 2 ? 2 : 0;
+    static constexpr size_t BYTES = (F_SLOTS + M_SLOTS) * F_BYTES + 2 * (IN_BYTES + X_BYTES);
 };
 
 template <int R, int FM>
@@ -82,10 +91,10 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
     if (a.stop && *a.stop) return;  // the level has met its stopping rule
 
     extern __shared__ __align__(16) unsigned char smem[];
-    float* s_f0 = reinterpret_cast<float*>(smem);                                   // [2][FH*FW]
-    float* s_mm0 = s_f0 + (DBL ? 2 * FH * FW : 0);                                  // [2][FH*FW] (DBL)
-    float* s_in0 = reinterpret_cast<float*>(smem + 2 * L::F_BYTES * (DBL ? 2 : 1));  // [2][3][H][PW]
-    float* s_x0 = s_in0 + 2 * 3 * H * PW;                                           // [2][3][H][QTX]
+    float* s_f0 = reinterpret_cast<float*>(smem);                                         // [4][FH*FW]
+    float* s_mm0 = s_f0 + L::F_SLOTS * FH * FW;                                           // [2][FH*FW] (DBL)
+    float* s_in0 = reinterpret_cast<float*>(smem + (L::F_SLOTS + L::M_SLOTS) * L::F_BYTES);  // [2][3][H][PW]
+    float* s_x0 = s_in0 + 2 * 3 * H * PW;                                                 // [2][3][H][QTX]
 
     const int lb = xcd_logical_block(bid, a.nblocks);
     const int bx = lb % a.tiles_x;
@@ -145,42 +154,52 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
     // arguments (scalar work the compiler hoists; none is captured by a lambda)
     const long cb = N * 4;
     const int pb = plane * 4;
-    // registers: the f (and m) region of the next plane; per-point data in two sets
+    // registers: the f region of the plane after next and the m region of the
+    // next plane; per-point data in two sets. The f region is staged for
+    // planes z0 - 1 .. z1 (clamped to the volume), so the force takes its z
+    // neighbours, like its in-plane ones, from LDS.
     float pf[NF], pmf[DBL ? NF : 1];
     struct Pt {
-        float r0[NP], r1[NP], r2[NP], m[NP], fu[NP], fd[NP], mu[DBL ? NP : 1], md[DBL ? NP : 1];
+        float r0[NP], r1[NP], r2[NP], m[NP], mu[DBL ? NP : 1], md[DBL ? NP : 1];
     };
     Pt setA, setB;
-    auto fetch_region = [&](int p) {  // f (and m) region of plane p (clamped: always valid)
-        const int so = (z0 + min(p, nplanes - 1)) * pb;
+    auto fetch_f = [&](int p) {  // f region of plane z0 + p (clamped: always valid)
         if (FORCE) {
+            const int so = clampi(z0 + p, a.nz) * pb;
             const Rsrc fb = make_rsrc(a.f, cb);
 #pragma unroll
             for (int q = 0; q < NF; ++q) pf[q] = ld(fb, foff[q] * 4, so);
         }
+    };
+    auto fetch_m = [&](int p) {  // m region of plane z0 + p (double force; clamped)
         if (DBL) {
+            const int so = (z0 + min(p, nplanes - 1)) * pb;
             const Rsrc mb = make_rsrc(a.m, cb);
 #pragma unroll
             for (int q = 0; q < NF; ++q) pmf[q] = ld(mb, foff[q] * 4, so);
         }
+    };
+    // LDS slot of the f region of relative plane p (-1 .. nplanes)
+    auto f_slot = [&](int p) { return s_f0 + ((p + 1) & 3) * (FH * FW); };
+    auto stash_f = [&](int p) {
+        float* sf = f_slot(p);
+#pragma unroll
+        for (int q = 0; q < NF; ++q)
+            if (fval[q]) sf[t + q * NT] = pf[q];
     };
     auto fetch_points = [&](Pt& d, int p) {
         const int z = z0 + min(p, nplanes - 1);
         const int so = z * pb;
         const int su = clampi(z + 1, a.nz) * pb, sd = clampi(z - 1, a.nz) * pb;
         const Rsrc rb0 = make_rsrc(a.r, cb), rb1 = make_rsrc(a.r + N, cb), rb2 = make_rsrc(a.r + 2 * N, cb);
-        const Rsrc fb = make_rsrc(a.f, cb), mb = make_rsrc(a.m, cb);
+        const Rsrc mb = make_rsrc(a.m, cb);
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
             const int vo = pofs[q] * 4;
             d.r0[q] = ld(rb0, vo, so);
             d.r1[q] = ld(rb1, vo, so);
             d.r2[q] = ld(rb2, vo, so);
-            if (FORCE) {
-                d.m[q] = ld(mb, vo, so);
-                d.fu[q] = ld(fb, vo, su);
-                d.fd[q] = ld(fb, vo, sd);
-            }
+            if (FORCE) d.m[q] = ld(mb, vo, so);
             if (DBL) {
                 d.mu[q] = ld(mb, vo, su);
                 d.md[q] = ld(mb, vo, sd);
@@ -192,23 +211,23 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
     // s - 1 (consumed here) and receives that of plane s + 1
     auto step = [&](int s, const int par, Pt& cur) {
         const int ps = s, pc = s - 1, px = s - 2, py = s - 3;
-        // stash the f (and m) region of plane s, request that of plane s + 1
-        if (FORCE && ps < nplanes) {
-            float* sf = s_f0 + par * (FH * FW);
+        // stash the f region of plane s + 1 (and the m region of plane s),
+        // request those of planes s + 2 (and s + 1)
+        if (FORCE && ps + 1 <= nplanes) stash_f(ps + 1);
+        if (DBL && ps < nplanes) {
+            float* smm = s_mm0 + par * (FH * FW);
 #pragma unroll
             for (int q = 0; q < NF; ++q)
-                if (fval[q]) sf[t + q * NT] = pf[q];
-            if (DBL) {
-                float* smm = s_mm0 + par * (FH * FW);
-#pragma unroll
-                for (int q = 0; q < NF; ++q)
-                    if (fval[q]) smm[t + q * NT] = pmf[q];
-            }
+                if (fval[q]) smm[t + q * NT] = pmf[q];
         }
-        fetch_region(ps + 1);
-        // force of plane s - 1 on the tile plus halo: r~ = r - u
+        fetch_f(ps + 2);
+        fetch_m(ps + 1);
+        // force of plane s - 1 on the tile plus halo: r~ = r - u (f of planes
+        // s - 2, s - 1, s were stashed in earlier steps)
         if (pc >= 0 && pc < nplanes) {
-            const float* sf = s_f0 + (par ^ 1) * (FH * FW);
+            const float* sf = f_slot(pc);
+            const float* sfu = f_slot(pc + 1);
+            const float* sfd = f_slot(pc - 1);
             const float* smm = s_mm0 + (par ^ 1) * (FH * FW);
             float* sin = s_in0 + (par ^ 1) * (3 * H * PW);
             const int zoff = (z0 + pc) * plane;
@@ -220,7 +239,7 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
                     const float fcv = sf[fc_[q]];
                     const float gxv = (sf[fxp_[q]] - sf[fxm_[q]]) * 0.5f;
                     const float gyv = (sf[fyp_[q]] - sf[fym_[q]]) * 0.5f;
-                    const float gzv = (cur.fu[q] - cur.fd[q]) * 0.5f;
+                    const float gzv = (sfu[fc_[q]] - sfd[fc_[q]]) * 0.5f;
                     const float d = cur.m[q] - fcv;
                     const float den = gxv * gxv + gyv * gyv + gzv * gzv + d * d;
                     if (den > 0.0f && fabsf(d) >= a.eps_d) {
@@ -311,7 +330,16 @@ __device__ __forceinline__ void plane_pipe_body(const PlaneArgs& a, const int bi
         __syncthreads();
     };
 
-    fetch_region(0);
+    // the f regions of planes z0 - 1 and z0 go to LDS up front (visible to
+    // every wave after step 0's barrier, before the first force in step 1)
+    if (FORCE) {
+        fetch_f(-1);
+        stash_f(-1);
+        fetch_f(0);
+        stash_f(0);
+    }
+    fetch_f(1);
+    fetch_m(0);
     fetch_points(setB, 0);  // plane 0's point data, consumed in step 1 (odd)
     const int nsteps = nplanes + 3;
     for (int s = 0; s < nsteps; s += 2) {
@@ -338,6 +366,7 @@ template <int R, int FM>
 void launch_pipe_one(const PlaneArgs& a, hipStream_t st)
 {
     constexpr size_t lds = PipeLds<R, FM>::BYTES;
+    static_assert(lds <= 160 * 1024, "fits the LDS of one CU");
     lds_limit((const void*)k_plane_pipe<R, FM>, lds);
     hipLaunchKernelGGL((k_plane_pipe<R, FM>), dim3(a.nblocks), dim3(QTX * QTY), lds, st, a);
 }
