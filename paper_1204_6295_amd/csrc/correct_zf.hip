@@ -273,8 +273,8 @@ int correct_zf_resident(const int patch[3])
 
 bool correct_zf_applies(Dims d, const int patch[3])
 {
-    // (at 15^3 the region columns take 144 registers, one workgroup per CU:
-    // the x -> y -> z sweep is faster there, 232 against 319 us at 512^2 x 160)
+    // (at 15^3 the 59 KB of LDS leave two workgroups per CU and the x -> y -> z
+    // sweep is faster: 232 against 241 us per launch at 512^2 x 160)
     (void)d;
     return patch[0] == patch[1] && patch[1] == patch[2] && patch[2] <= 13;
 }
