@@ -4,11 +4,11 @@
 //   k_plane_pipe  one workgroup per 32 x 32 tile and chunk of z planes. It
 //               forms r~ = r - u on the tile plus the R-voxel Gaussian halo
 //               (R = ceil(3 sigma)), u being the Eq. 1 demons force on the
-//               corrected image f (the f plane is staged in LDS for the
-//               in-plane gradient), then runs the x and y passes out of LDS
-//               with register-blocked runs of 8 (x) and 4 (y) outputs and writes the
-//               xy-filtered field q; the four stages are software-pipelined
-//               over planes.
+//               corrected image f (three f planes are staged in LDS for the
+//               gradient), then runs the x and y passes out of LDS with
+//               register-blocked runs of 8 (x) and 4 (y) outputs and writes
+//               the xy-filtered field q; the four stages are
+//               software-pipelined over planes.
 //   k_smooth_z  one thread per (x, y) column over a chunk of z: a register
 //               ring of the last 2R + 1 planes of q gives the z pass, and the
 //               CT is warped with the new field for the next iteration. Halo
