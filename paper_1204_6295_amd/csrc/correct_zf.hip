@@ -1,22 +1,24 @@
 // Patch moments (Eq. 3) and the moment-matching correction (Eq. 5-6) for
 // isotropic patches on large volumes, z first.
 //
-// A 512-thread workgroup owns a 32 x 32 column tile and a chunk of output
-// planes. Every column of the tile plus its in-plane patch halo keeps the
-// FP64 sums of m and m^2 over its z window in registers, advanced by one
-// plane per step (add the plane entering the window, subtract the one
-// leaving it; both loads are requested one step ahead). Per output plane:
+// A workgroup of 512 threads (768 at 15^3) owns a 32 x 32 column tile and a
+// chunk of output planes. Every column of the tile plus its in-plane patch
+// halo keeps the FP64 sums of m and m^2 over its z window in registers,
+// advanced by one plane per step (add the plane entering the window,
+// subtract the one leaving it; both loads are requested one step ahead).
+// Per output plane:
 //   store   the column sums in LDS;                         barrier
 //   x pass  sliding sums along x of those, 4 outputs per item, one lane per
 //           region row (row-fastest lanes: conflict-free 16-byte accesses);
 //                                                            barrier
-//   y pass  sliding sums along y, 2 outputs per item (one item per
-//           thread), then the epilogue I'_s = E(M) + STD(M) Y at those voxels.
+//   y pass  sliding sums along y, 2 outputs per item (512 items), then
+//           the epilogue I'_s = E(M) + STD(M) Y at those voxels.
 // The x and y passes run only on output planes (the z halo costs one add
 // per column and plane). The kernel is held to 80 VGPRs (six waves per
 // SIMD), so with its 51 KB of LDS at 11^3 three workgroups share a CU and
 // one workgroup's barrier waits overlap the others' work.
-// Used for isotropic patches up to 13^3 at every volume size.
+// Used for isotropic patches up to 15^3 at every volume size (batches: up to
+// 13^3).
 #include <cmath>
 
 #include "kernels.h"
@@ -26,7 +28,10 @@ namespace disc {
 namespace {
 
 constexpr int ZTS = 32;   // output tile edge
-constexpr int ZFT = 512;  // threads per workgroup
+// threads per workgroup: 512 up to 13^3; 768 at 15^3, whose 46 x 46 region
+// columns then take three per thread
+template <int PZ>
+constexpr int zf_threads() { return PZ <= 13 ? 512 : 768; }
 constexpr int XRUN = 4;   // outputs per x item
 constexpr int YRUN = 2;   // outputs per y item (every thread takes one)
 constexpr int ZPF = 1;    // steps of m loads in flight (two would not fit in 80 VGPRs)
@@ -52,6 +57,7 @@ struct ZfLds {
 template <int PZ, int R>
 __device__ __forceinline__ void zf_body(const ZfArgs& a, const int bid)
 {
+    constexpr int ZFT = zf_threads<PZ>();
     constexpr int RZ = PZ / 2;
     using L = ZfLds<R>;
     constexpr int W = L::W, ZP = L::ZP, XP = L::XP;
@@ -204,13 +210,13 @@ __device__ __forceinline__ void zf_body(const ZfArgs& a, const int bid)
 }
 
 template <int PZ, int R>
-__global__ __launch_bounds__(ZFT, 6) void k_correct_zf(ZfArgs a)
+__global__ __launch_bounds__(zf_threads<PZ>(), 6) void k_correct_zf(ZfArgs a)
 {
     zf_body<PZ, R>(a, blockIdx.x);
 }
 
 template <int PZ, int R>
-__global__ __launch_bounds__(ZFT, 6) void k_correct_zf_batch(Batch<ZfArgs> b)
+__global__ __launch_bounds__(zf_threads<PZ>(), 6) void k_correct_zf_batch(Batch<ZfArgs> b)
 {
     const int v = batch_volume(b.start, b.n, blockIdx.x);
     zf_body<PZ, R>(b.v[v], blockIdx.x - b.start[v]);
@@ -239,7 +245,7 @@ void launch_zf_batch_one(const Batch<ZfArgs>& b, hipStream_t st)
     constexpr int R = PZ / 2;
     constexpr size_t lds = ZfLds<R>::BYTES;
     lds_limit((const void*)k_correct_zf_batch<PZ, R>, lds);
-    hipLaunchKernelGGL((k_correct_zf_batch<PZ, R>), dim3(b.start[b.n]), dim3(ZFT), lds, st, b);
+    hipLaunchKernelGGL((k_correct_zf_batch<PZ, R>), dim3(b.start[b.n]), dim3(zf_threads<PZ>()), lds, st, b);
 }
 
 template <int PZ>
@@ -248,7 +254,7 @@ void launch_zf_one(const ZfArgs& a, hipStream_t st)
     constexpr int R = PZ / 2;
     constexpr size_t lds = ZfLds<R>::BYTES;
     lds_limit((const void*)k_correct_zf<PZ, R>, lds);
-    hipLaunchKernelGGL((k_correct_zf<PZ, R>), dim3(a.nblocks), dim3(ZFT), lds, st, a);
+    hipLaunchKernelGGL((k_correct_zf<PZ, R>), dim3(a.nblocks), dim3(zf_threads<PZ>()), lds, st, a);
 }
 
 }  // namespace
@@ -265,7 +271,8 @@ int correct_zf_resident(const int patch[3])
         case 7: lds = ZfLds<3>::BYTES; break;
         case 9: lds = ZfLds<4>::BYTES; break;
         case 11: lds = ZfLds<5>::BYTES; break;
-        default: lds = ZfLds<6>::BYTES; break;
+        case 13: lds = ZfLds<6>::BYTES; break;
+        default: lds = ZfLds<7>::BYTES; break;
     }
     const int by_lds = (int)((160 * 1024) / lds);
     return by_lds < 3 ? by_lds : 3;
@@ -273,10 +280,10 @@ int correct_zf_resident(const int patch[3])
 
 bool correct_zf_applies(Dims d, const int patch[3])
 {
-    // (at 15^3 the 59 KB of LDS leave two workgroups per CU and the x -> y -> z
-    // sweep is faster: 232 against 241 us per launch at 512^2 x 160)
+    // (at 15^3: 768 threads, two workgroups per CU by LDS; 224.6 against
+    // 232 us for the x -> y -> z sweep at 512^2 x 160, 241 us with 512 threads)
     (void)d;
-    return patch[0] == patch[1] && patch[1] == patch[2] && patch[2] <= 13;
+    return patch[0] == patch[1] && patch[1] == patch[2] && patch[2] <= 15;
 }
 
 hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, const int patch[3], hipStream_t st,
@@ -297,6 +304,7 @@ hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, 
         case 9: launch_zf_one<9>(a, st); break;
         case 11: launch_zf_one<11>(a, st); break;
         case 13: launch_zf_one<13>(a, st); break;
+        case 15: launch_zf_one<15>(a, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -110,8 +110,8 @@ size_t median_scratch_bytes();
 hipError_t launch_mask_consts(const float* a_vals, long n, const double* dhu, float hu0, float lo_frac,
                               float hi_frac, float h, void* scratch, float* consts, hipStream_t st);
 
-// Moments + correction, z first (isotropic patches up to 13^3; about
-// `target` workgroups of 512 threads).
+// Moments + correction, z first (isotropic patches up to 15^3, batches up to
+// 13^3; about `target` workgroups of 512 threads, 768 at 15^3).
 bool correct_zf_applies(Dims d, const int patch[3]);
 int correct_zf_resident(const int patch[3]);  // workgroups of the sweep per CU
 hipError_t launch_correct_zf(const float* m, const float* ys, float* f, Dims d, const int patch[3], hipStream_t st,

@@ -2,10 +2,10 @@
 
 The 512x512x160 head-and-neck pair with patch 15^3 and sigma 2 runs the
 finest level of that registration with its own launch geometry: the
-x -> y -> z moments sweep on 32 x 32 tiles (15^3 is beyond the z-first
-sweep), the force + xy pipeline and the ring z pass with the fused next
-warp, each on 32 x 32-column tiles (16 x 16 per plane) with the z chunks
-this size selects. Each step runs through the C ABI on identical FP32 inputs
+z-first moments sweep with 768-thread workgroups (the 15^3 variant), the
+force + xy pipeline and the ring z pass with the fused next warp, each on
+32 x 32-column tiles (16 x 16 per plane) with the z chunks this size
+selects. Each step runs through the C ABI on identical FP32 inputs
 from a mid-registration state and is compared with the FP64 oracle at every
 voxel: max|gpu - ref| / max|ref| <= 1e-4 per output array, and the force per
 voxel to 1e-5 voxel absolute.
